@@ -1,0 +1,376 @@
+"""Seeded generators for the synthetic QP workloads.
+
+Every generator is deterministic given its seed (numpy PCG64 through
+``np.random.default_rng``).  The arrays are produced once on the host; the
+oracle and the GPU library both consume exactly these arrays.
+
+The paper evaluates on synthetic random-QP, control and portfolio classes
+(Sec. 6.1, experimental set-up); the shapes below are our own stand-ins for
+those classes, not reproductions of any third-party generator.
+
+CSR convention: int32 ``rowptr``/``col``, float64 values, column indices sorted
+within each row, Q stored as a full symmetric matrix (both triangles).
+Row types: 0 = equality row (A_i x = b_i), 1 = ``>=`` row (A_i x >= b_i).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+EQ = 0
+GE = 1
+
+
+@dataclass
+class QPInstance:
+    name: str
+    n: int
+    m: int
+    q_rowptr: np.ndarray
+    q_col: np.ndarray
+    q_val: np.ndarray
+    a_rowptr: np.ndarray
+    a_col: np.ndarray
+    a_val: np.ndarray
+    c: np.ndarray
+    b: np.ndarray
+    l: np.ndarray
+    u: np.ndarray
+    row_type: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def q_nnz(self) -> int:
+        return int(self.q_rowptr[-1])
+
+    @property
+    def a_nnz(self) -> int:
+        return int(self.a_rowptr[-1])
+
+    def Q(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.q_val, self.q_col, self.q_rowptr), shape=(self.n, self.n))
+
+    def A(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.a_val, self.a_col, self.a_rowptr), shape=(self.m, self.n))
+
+    def dense(self):
+        return self.Q().toarray(), self.A().toarray()
+
+
+def _to_csr(mat) -> tuple:
+    mat = sp.csr_matrix(mat)
+    mat.sum_duplicates()
+    mat.sort_indices()
+    return (mat.indptr.astype(np.int32), mat.indices.astype(np.int32),
+            mat.data.astype(np.float64))
+
+
+def csr_from_dense(M: np.ndarray) -> tuple:
+    """CSR (rowptr, col, val) of the nonzero pattern of a dense matrix."""
+    return _to_csr(sp.csr_matrix(np.asarray(M, dtype=np.float64)))
+
+
+def _make(name, Q, A, c, b, l, u, row_type, meta=None) -> QPInstance:
+    qr, qc, qv = _to_csr(Q)
+    ar, ac, av = _to_csr(A)
+    n = Q.shape[0]
+    m = A.shape[0]
+    return QPInstance(name, n, m, qr, qc, qv, ar, ac, av,
+                      np.ascontiguousarray(c, dtype=np.float64),
+                      np.ascontiguousarray(b, dtype=np.float64),
+                      np.ascontiguousarray(l, dtype=np.float64),
+                      np.ascontiguousarray(u, dtype=np.float64),
+                      np.ascontiguousarray(row_type, dtype=np.uint8),
+                      meta or {})
+
+
+def _distinct_cols(rng, nrows: int, ncols: int, k: int, exclude_self: bool = False):
+    """(nrows, k) matrix of distinct uniform column indices per row, sorted."""
+    k = min(k, ncols - (1 if exclude_self else 0))
+    cols = rng.integers(0, ncols, size=(nrows, k), dtype=np.int64)
+    rows = np.arange(nrows, dtype=np.int64)[:, None]
+    while True:
+        cols.sort(axis=1)
+        bad = np.zeros(nrows, dtype=bool)
+        if k > 1:
+            bad |= (np.diff(cols, axis=1) == 0).any(axis=1)
+        if exclude_self:
+            bad |= (cols == rows).any(axis=1)
+        nb = int(bad.sum())
+        if nb == 0:
+            return cols
+        cols[bad] = rng.integers(0, ncols, size=(nb, k), dtype=np.int64)
+
+
+def _diag_dominant_from_offdiag(off: sp.spmatrix) -> sp.csr_matrix:
+    off = sp.csr_matrix(off)
+    off.sum_duplicates()
+    off.setdiag(0.0)
+    off.eliminate_zeros()
+    d = np.asarray(abs(off).sum(axis=1)).ravel() + 1.0
+    return sp.csr_matrix(off + sp.diags(d))
+
+
+# ---------------------------------------------------------------------------
+# Tiny random QP: n=100, m=50 (30 EQ, 20 GE), A 10 % dense, Q = S+S^T + diag.
+# ---------------------------------------------------------------------------
+def tiny_random_qp(seed: int = 1, n: int = 100, m: int = 50, n_eq: int = 30,
+                   a_density: float = 0.10, s_density: float = 0.05,
+                   bound: float = 10.0) -> QPInstance:
+    rng = np.random.default_rng(seed)
+    A = np.where(rng.random((m, n)) < a_density, rng.standard_normal((m, n)), 0.0)
+    S = np.where(rng.random((n, n)) < s_density, rng.standard_normal((n, n)), 0.0)
+    np.fill_diagonal(S, 0.0)
+    Q = _diag_dominant_from_offdiag(sp.csr_matrix(S + S.T))
+    c = rng.standard_normal(n)
+    l = np.full(n, -np.inf)
+    u = np.full(n, np.inf)
+    bounded = rng.permutation(n)[: n // 2]
+    l[bounded] = -bound
+    u[bounded] = bound
+    x0 = rng.uniform(-1.0, 1.0, n)
+    b = A @ x0
+    row_type = np.array([EQ] * n_eq + [GE] * (m - n_eq), dtype=np.uint8)
+    b[n_eq:] -= rng.uniform(0.0, 1.0, m - n_eq)
+    return _make(f"tiny_random_n{n}_m{m}_s{seed}", Q, sp.csr_matrix(A), c, b, l, u,
+                 row_type, {"x_feasible": x0})
+
+
+# ---------------------------------------------------------------------------
+# Large sparse random QP: n=1e6, m=5e5 (half EQ, half GE), A 10 nnz/row,
+# Q = S + S^T (S 5 nnz/row) + diagonal making it diagonally dominant, x >= 0.
+# ---------------------------------------------------------------------------
+def large_random_qp(seed: int = 2, n: int = 1_000_000, m: int = 500_000,
+                    a_per_row: int = 10, s_per_row: int = 5) -> QPInstance:
+    rng = np.random.default_rng(seed)
+    acols = _distinct_cols(rng, m, n, a_per_row)
+    k = acols.shape[1]
+    avals = rng.standard_normal((m, k))
+    A = sp.csr_matrix((avals.ravel(), acols.ravel(), np.arange(0, m * k + 1, k)), shape=(m, n))
+    scols = _distinct_cols(rng, n, n, s_per_row, exclude_self=True)
+    ks = scols.shape[1]
+    svals = rng.standard_normal((n, ks))
+    srows = np.repeat(np.arange(n), ks)
+    S = sp.csr_matrix((svals.ravel(), (srows, scols.ravel())), shape=(n, n))
+    Q = _diag_dominant_from_offdiag(S + S.T)
+    c = rng.standard_normal(n)
+    l = np.zeros(n)
+    u = np.full(n, np.inf)
+    x0 = rng.uniform(0.0, 1.0, n)
+    b = A @ x0
+    n_eq = m // 2
+    row_type = np.array([EQ] * n_eq + [GE] * (m - n_eq), dtype=np.uint8)
+    b[n_eq:] -= rng.uniform(0.0, 1.0, m - n_eq)
+    return _make(f"large_random_n{n}_m{m}_s{seed}", Q, A, c, b, l, u, row_type,
+                 {"x_feasible": x0})
+
+
+# ---------------------------------------------------------------------------
+# Factor-model portfolio QP: variables (x, y), x in R^{n_assets} (x >= 0),
+# y in R^k (free).  min x^T D x + y^T y - mu^T x,  y = F^T x,  1^T x = budget.
+# In 1/2 form: Q = diag(2D, 2I), c = (-mu, 0).
+# ---------------------------------------------------------------------------
+def _sparse_factor(rng, n_assets: int, k: int, density: float) -> sp.csc_matrix:
+    rows, cols = [], []
+    for j in range(k):
+        cnt = int(rng.binomial(n_assets, density))
+        r = np.unique(rng.integers(0, n_assets, size=cnt))
+        rows.append(r)
+        cols.append(np.full(r.size, j))
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = rng.standard_normal(rows.size)
+    return sp.csc_matrix((vals, (rows, cols)), shape=(n_assets, k))
+
+
+def _portfolio_from_parts(name, D, F, mu, budget, k) -> QPInstance:
+    n_assets = D.size
+    n = n_assets + k
+    Q = sp.diags(np.concatenate([2.0 * D, np.full(k, 2.0)]))
+    c = np.concatenate([-mu, np.zeros(k)])
+    # rows 0..k-1: y_i - (F^T x)_i = 0 ; row k: 1^T x = budget
+    Ft = sp.csr_matrix(F.T)
+    top = sp.hstack([-Ft, sp.identity(k, format="csr")])
+    bottom = sp.csr_matrix((np.ones(n_assets), (np.zeros(n_assets, dtype=np.int64),
+                                                np.arange(n_assets))), shape=(1, n))
+    A = sp.vstack([top, bottom]).tocsr()
+    b = np.zeros(k + 1)
+    b[k] = budget
+    l = np.concatenate([np.zeros(n_assets), np.full(k, -np.inf)])
+    u = np.full(n, np.inf)
+    row_type = np.zeros(k + 1, dtype=np.uint8)
+    return _make(name, Q, A, c, b, l, u, row_type, {"n_assets": n_assets, "k": k})
+
+
+def portfolio_qp(seed: int = 3, n_assets: int = 500_000, k: int = 1000,
+                 f_density: float = 0.01, budget: float = 1.0) -> QPInstance:
+    rng = np.random.default_rng(seed)
+    F = _sparse_factor(rng, n_assets, k, f_density)
+    D = rng.uniform(0.0, np.sqrt(k) * 0.1, n_assets)
+    mu = rng.standard_normal(n_assets)
+    return _portfolio_from_parts(f"portfolio_n{n_assets}_k{k}_s{seed}", D, F, mu, budget, k)
+
+
+@dataclass
+class PortfolioFamily:
+    """A parametrised family sharing D and F; instance i has its own mu and budget."""
+    base: QPInstance
+    mu: np.ndarray        # (count, n_assets)
+    budget: np.ndarray    # (count,)
+    mu_bar: np.ndarray
+    mu_sigma: float
+
+    @property
+    def count(self) -> int:
+        return self.budget.size
+
+    def c_of(self, i: int) -> np.ndarray:
+        k = self.base.meta["k"]
+        return np.concatenate([-self.mu[i], np.zeros(k)])
+
+    def b_of(self, i: int) -> np.ndarray:
+        b = np.zeros(self.base.m)
+        b[-1] = self.budget[i]
+        return b
+
+    def instance(self, i: int) -> QPInstance:
+        bi = self.base
+        return QPInstance(f"{bi.name}_i{i}", bi.n, bi.m, bi.q_rowptr, bi.q_col, bi.q_val,
+                          bi.a_rowptr, bi.a_col, bi.a_val, self.c_of(i), self.b_of(i),
+                          bi.l, bi.u, bi.row_type, dict(bi.meta))
+
+    def batch(self, idx) -> "BatchInstances":
+        return concat_batch([self.instance(int(i)) for i in idx])
+
+
+def portfolio_family(seed: int = 5, n_assets: int = 5000, k: int = 100, count: int = 20000,
+                     f_density: float = 0.01, mu_sigma: float = 0.1,
+                     budget_lo: float = 0.5, budget_hi: float = 1.5) -> PortfolioFamily:
+    rng = np.random.default_rng(seed)
+    F = _sparse_factor(rng, n_assets, k, f_density)
+    D = rng.uniform(0.0, np.sqrt(k) * 0.1, n_assets)
+    mu_bar = rng.standard_normal(n_assets)
+    base = _portfolio_from_parts(f"portfolio_family_n{n_assets}_k{k}_s{seed}", D, F, mu_bar,
+                                 1.0, k)
+    mu = mu_bar[None, :] + mu_sigma * rng.standard_normal((count, n_assets))
+    budget = rng.uniform(budget_lo, budget_hi, count)
+    return PortfolioFamily(base, mu, budget, mu_bar, mu_sigma)
+
+
+# ---------------------------------------------------------------------------
+# MPC-style QP: z = (x_0..x_T, u_0..u_{T-1}); x_0 = x_init,
+# x_{t+1} - A_t x_t - B_t u_t = 0; diagonal state/input weights; box bounds.
+# ---------------------------------------------------------------------------
+def mpc_qp(rng, T: int, nx: int, nu: int, name: str = "mpc",
+           state_bound_cap: float = 1e3) -> QPInstance:
+    n = (T + 1) * nx + T * nu
+    m = (T + 1) * nx
+    At = np.eye(nx)[None] + 0.1 * rng.standard_normal((T, nx, nx))
+    Bt = 0.1 * rng.standard_normal((T, nx, nu))
+    qd = rng.uniform(0.1, 10.0, (T + 1) * nx)
+    rd = rng.uniform(0.1, 10.0, T * nu)
+    x_init = rng.uniform(-1.0, 1.0, nx)
+    u_sim = rng.uniform(-0.5, 0.5, (T, nu))
+    xs = [x_init]
+    for t in range(T):
+        xs.append(At[t] @ xs[-1] + Bt[t] @ u_sim[t])
+    xmax = float(np.max(np.abs(np.array(xs))))
+    xb = max(10.0, 2.0 * xmax)
+    if xb > state_bound_cap:
+        xb = np.inf
+    ix = lambda t, j: t * nx + j  # noqa: E731
+    iu = lambda t, j: (T + 1) * nx + t * nu + j  # noqa: E731
+    rows, cols, vals = [], [], []
+    for j in range(nx):
+        rows.append(j); cols.append(ix(0, j)); vals.append(1.0)
+    for t in range(T):
+        for j in range(nx):
+            r = (t + 1) * nx + j
+            for q in range(nx):
+                rows.append(r); cols.append(ix(t, q)); vals.append(-At[t, j, q])
+            rows.append(r); cols.append(ix(t + 1, j)); vals.append(1.0)
+            for q in range(nu):
+                rows.append(r); cols.append(iu(t, q)); vals.append(-Bt[t, j, q])
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    Q = sp.diags(np.concatenate([qd, rd]))
+    c = np.zeros(n)
+    b = np.zeros(m)
+    b[:nx] = x_init
+    l = np.concatenate([np.full((T + 1) * nx, -xb), np.full(T * nu, -1.0)])
+    u = -l
+    row_type = np.zeros(m, dtype=np.uint8)
+    z_sim = np.concatenate([np.array(xs).ravel(), u_sim.ravel()])
+    return _make(name, Q, A, c, b, l, u, row_type,
+                 {"T": T, "nx": nx, "nu": nu, "x_feasible": z_sim, "state_bound": xb})
+
+
+def mpc_batch(seed: int = 4, count: int = 4096, T_range=(10, 100), nx_range=(4, 12),
+              nu_range=(2, 4)) -> "BatchInstances":
+    insts = []
+    for i in range(count):
+        rng = np.random.default_rng([seed, i])
+        T = int(rng.integers(T_range[0], T_range[1] + 1))
+        nx = int(rng.integers(nx_range[0], nx_range[1] + 1))
+        nu = int(rng.integers(nu_range[0], nu_range[1] + 1))
+        insts.append(mpc_qp(rng, T, nx, nu, name=f"mpc_s{seed}_i{i}"))
+    return concat_batch(insts)
+
+
+# ---------------------------------------------------------------------------
+# Segment-CSR batch: instances concatenated; row pointers are global offsets
+# into the concatenated nnz arrays, column indices stay local to the instance.
+# ---------------------------------------------------------------------------
+@dataclass
+class BatchInstances:
+    count: int
+    var_off: np.ndarray   # int64 [B+1]
+    row_off: np.ndarray   # int64 [B+1]
+    q_rowptr: np.ndarray  # int32 [sum n + 1]  (global nnz offsets)
+    q_col: np.ndarray     # int32 local column ids
+    q_val: np.ndarray
+    a_rowptr: np.ndarray  # int32 [sum m + 1]
+    a_col: np.ndarray
+    a_val: np.ndarray
+    c: np.ndarray
+    b: np.ndarray
+    l: np.ndarray
+    u: np.ndarray
+    row_type: np.ndarray
+    names: list
+
+    def instance(self, i: int) -> QPInstance:
+        v0, v1 = int(self.var_off[i]), int(self.var_off[i + 1])
+        r0, r1 = int(self.row_off[i]), int(self.row_off[i + 1])
+        qp = self.q_rowptr[v0:v1 + 1].astype(np.int64)
+        ap = self.a_rowptr[r0:r1 + 1].astype(np.int64)
+        return QPInstance(self.names[i], v1 - v0, r1 - r0,
+                          (qp - qp[0]).astype(np.int32), self.q_col[qp[0]:qp[-1]].copy(),
+                          self.q_val[qp[0]:qp[-1]].copy(),
+                          (ap - ap[0]).astype(np.int32), self.a_col[ap[0]:ap[-1]].copy(),
+                          self.a_val[ap[0]:ap[-1]].copy(),
+                          self.c[v0:v1].copy(), self.b[r0:r1].copy(),
+                          self.l[v0:v1].copy(), self.u[v0:v1].copy(),
+                          self.row_type[r0:r1].copy())
+
+
+def concat_batch(insts) -> BatchInstances:
+    B = len(insts)
+    var_off = np.zeros(B + 1, dtype=np.int64)
+    row_off = np.zeros(B + 1, dtype=np.int64)
+    for i, q in enumerate(insts):
+        var_off[i + 1] = var_off[i] + q.n
+        row_off[i + 1] = row_off[i] + q.m
+    qnnz = np.cumsum([0] + [q.q_nnz for q in insts])
+    annz = np.cumsum([0] + [q.a_nnz for q in insts])
+    if qnnz[-1] >= 2**31 or annz[-1] >= 2**31:
+        raise ValueError("batch too large for int32 row pointers")
+    q_rowptr = np.concatenate([insts[i].q_rowptr[:-1].astype(np.int64) + qnnz[i] for i in range(B)]
+                              + [np.array([qnnz[-1]])]).astype(np.int32)
+    a_rowptr = np.concatenate([insts[i].a_rowptr[:-1].astype(np.int64) + annz[i] for i in range(B)]
+                              + [np.array([annz[-1]])]).astype(np.int32)
+    cat = lambda attr: np.concatenate([getattr(q, attr) for q in insts])  # noqa: E731
+    return BatchInstances(B, var_off, row_off, q_rowptr, cat("q_col"), cat("q_val"),
+                          a_rowptr, cat("a_col"), cat("a_val"), cat("c"), cat("b"),
+                          cat("l"), cat("u"), cat("row_type"), [q.name for q in insts])
