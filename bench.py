@@ -1,0 +1,178 @@
+"""Benchmark of the MI355X rAPDHG hot path.
+
+Workload: the large sparse random QP (n = 1e6 variables, m = 5e5 rows: 2.5e5
+equality + 2.5e5 '>=' rows; A with 10 N(0,1) nonzeros per row; Q = S + S' with
+S holding 5 N(0,1) off-diagonal nonzeros per row plus a diagonal making Q
+diagonally dominant; c ~ N(0,1); x >= 0; b feasible from x0 ~ U(0,1)), FP64
+CSR, seeded synthetic data standing in for the paper's large random-QP class.
+
+One step = one qp_solve of ITERS iterations (eps = 0, so it never stops
+early): ITERS x (dual kernel + primal kernel), a KKT evaluation of z and z-bar
+every 64 iterations, the device-side restart / primal-weight / step-size
+decision and restart application.  value = iterations per second over the K
+timed steps.  Inputs are resident in HBM (copied at qp_create) before timing.
+
+Also reported: per-kernel hipEvent durations of the dual and primal kernels
+recorded over the timed region (settings.profile = 1: direct launches, an
+event pair around each kernel on the library's stream), the roofline of the
+dominant (primal) kernel from its algorithmic bytes, wall time to relKKT 1e-4
+and 1e-6, and the CPU oracle's iteration rate on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--iters ITERS]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rAPDHG iters/s + time-to-1e-6 KKT; SpMV HBM GB/s % peak; warm vs cold"
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--iters", type=int, default=1024)
+    ap.add_argument("--no-tol", action="store_true", help="skip the time-to-tolerance solves")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--graph", action="store_true",
+                    help="time with graph replay instead of per-kernel hipEvents")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
+              "multi-GPU path; the sharding design is described in DESIGN.md.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2311_07710_amd as qpa
+    import qpgen
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t = time.time()
+    qp = qpgen.large_random_qp()
+    log(f"[bench] generated n={qp.n} m={qp.m} nnzA={qp.a_nnz} nnzQ={qp.q_nnz} "
+        f"in {time.time() - t:.1f}s")
+
+    t = time.time()
+    profile = 0 if args.graph else 1
+    settings = qpa.Settings(eps=0.0, max_iter=args.iters, profile=profile, use_graph=1)
+    solver = qpa.Solver(qp, settings)
+    create_s = time.time() - t
+    nA, nQ = solver.norms()
+    log(f"[bench] qp_create {create_s:.2f}s (incl. power iteration) ||A||={nA:.6g} ||Q||={nQ:.6g}")
+
+    for w in range(args.warmup):
+        solver.solve()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+
+    dual_ms = primal_ms = 0.0
+    dual_n = primal_n = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for k in range(args.steps):
+        _, _, r = solver.solve()
+        iters += r["iterations"]
+        if profile:
+            p = solver.profile()
+            dual_ms += p["dual_ms"]
+            primal_ms += p["primal_ms"]
+            dual_n += p["dual_launches"]
+            primal_n += p["primal_launches"]
+            dual_bytes, primal_bytes = p["dual_bytes"], p["primal_bytes"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"[bench] timed {args.steps} steps x {args.iters} iterations in {elapsed:.3f}s")
+    value = iters / elapsed
+    ms_per_step = 1000.0 * elapsed / args.steps
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "large sparse random QP, n=1e6, m=5e5 (half EQ, half GE), A 10 nnz/row, "
+                        "Q diag-dominant ~11 nnz/row, x>=0, FP64 CSR (seed 2)",
+            "n": qp.n, "m": qp.m, "nnz_A": qp.a_nnz, "nnz_Q": qp.q_nnz,
+            "iters_per_step": args.iters, "check_every": 64,
+            "timing": "graph replay" if args.graph else "direct launches + hipEvent per kernel",
+        },
+        "create_s": create_s,
+    }
+    if profile and primal_n:
+        d_avg = dual_ms / dual_n
+        p_avg = primal_ms / primal_n
+        p_gbs = primal_bytes / (p_avg * 1e-3) / 1e9
+        d_gbs = dual_bytes / (d_avg * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": "k_primal", "achieved": p_gbs,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": p_gbs / HBM_PEAK_GBS,
+                           "traffic": None, "avg_us": 1000.0 * p_avg,
+                           "algorithmic_bytes_per_launch": primal_bytes}
+        out["kernels"] = {
+            "k_dual": {"avg_us": 1000.0 * d_avg, "bytes": dual_bytes, "GB/s": d_gbs,
+                       "frac": d_gbs / HBM_PEAK_GBS, "launches": dual_n},
+            "k_primal": {"avg_us": 1000.0 * p_avg, "bytes": primal_bytes, "GB/s": p_gbs,
+                         "frac": p_gbs / HBM_PEAK_GBS, "launches": primal_n},
+            "iteration_frac": (dual_bytes + primal_bytes) / ((d_avg + p_avg) * 1e-3) / 1e9
+                              / HBM_PEAK_GBS,
+        }
+        log(f"[bench] k_dual {1000 * d_avg:.1f}us {d_gbs:.0f} GB/s | k_primal {1000 * p_avg:.1f}us "
+            f"{p_gbs:.0f} GB/s")
+
+    if not args.no_tol:
+        tt = {}
+        for eps in (1e-4, 1e-6):
+            with qpa.Solver(qp, qpa.Settings(eps=eps, norm_A=nA, norm_Q=nQ, max_iter=200000,
+                                             time_limit_s=120.0)) as s2:
+                t = time.perf_counter()
+                _, _, r = s2.solve()
+                dt = time.perf_counter() - t
+            tt[f"{eps:g}"] = {"seconds": dt, "iterations": r["iterations"],
+                              "restarts": r["restarts"], "rel_kkt": r["rel_kkt"],
+                              "status": r["status"]}
+            log(f"[bench] to relKKT {eps:g}: {dt:.3f}s, {r['iterations']} iterations, "
+                f"status {r['status']}, relKKT {r['rel_kkt']:.3e}")
+        out["time_to_tolerance"] = tt
+
+    if not args.no_cpu:
+        import oracle
+        onA, _ = oracle.norm_A(qp, 40, 1e-7)
+        onQ, _ = oracle.norm_Q(qp, 40, 1e-7)
+        n_it = 96
+        t = time.perf_counter()
+        _, _, ro, _ = oracle.solve(qp, oracle.OracleSettings(eps=0.0, max_iter=n_it, norm_A=onA,
+                                                             norm_Q=onQ))
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": ro["iterations"] / dt, "unit": "iters/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{n_it} rAPDHG iterations (3 KKT evaluations) of the "
+                                         "same full-size instance, single-threaded C oracle"}
+        log(f"[bench] cpu oracle {ro['iterations'] / dt:.2f} iters/s ({dt:.1f}s)")
+
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

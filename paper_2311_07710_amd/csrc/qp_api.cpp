@@ -1,0 +1,907 @@
+// qp_api.cpp -- host side of the C-ABI declared in include/qp.h.
+//
+// qp_create validates the CSR input, builds the device layouts (A as CSR and
+// P = [Q | -A'] as one CSR matrix whose A' entries appear in increasing row
+// order of A), partitions the rows of both into nnz-balanced blocks, uploads
+// everything and estimates ||A||_2, ||Q||_2 by power iteration.
+//
+// qp_solve runs rAPDHG (Algorithm 1 inner loop, Sec. 6 restarts/step sizes/
+// primal weight, Sec. 5 relKKT termination) entirely on the device: one check
+// interval = `interval` x (dual kernel, primal kernel) + KKT kernels + the
+// single-workgroup decision kernel + the restart kernel, replayed as one
+// captured hipGraph.  The host only enqueues intervals (two in flight) and
+// reads a small status record per interval.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "../../include/qp.h"
+#include "qp_batch.h"
+#include "qp_internal.h"
+
+using namespace qpk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return fail(_e == hipErrorOutOfMemory ? QP_ERR_OUT_OF_MEMORY : QP_ERR_DEVICE,   \
+                        "%s failed: %s", #expr, hipGetErrorString(_e));                     \
+    } while (0)
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    int alloc(size_t b) {
+        release();
+        bytes = b;
+        if (b == 0) return QP_OK;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(QP_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
+        }
+        return QP_OK;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+struct HostPartition {
+    std::vector<Block> blk;
+    std::vector<int32_t> lr, lr_first, lr_nchunk;
+};
+
+// Group consecutive rows into blocks of <= NNZ_BLK nonzeros and <= BS rows; a
+// longer row becomes its own sequence of NNZ_BLK-sized chunks.
+HostPartition partition_rows(const int32_t *rowptr, int64_t nrows) {
+    HostPartition hp;
+    int64_t r = 0;
+    while (r < nrows) {
+        const int64_t len = (int64_t)rowptr[r + 1] - rowptr[r];
+        if (len > NNZ_BLK) {
+            const int32_t nch = (int32_t)((len + NNZ_BLK - 1) / NNZ_BLK);
+            const int32_t id = (int32_t)hp.lr_first.size();
+            hp.lr_first.push_back((int32_t)hp.blk.size());
+            hp.lr_nchunk.push_back(nch);
+            for (int32_t ch = 0; ch < nch; ++ch) {
+                Block b;
+                b.row0 = (int32_t)r;
+                b.row1 = (int32_t)r + 1;
+                b.e0 = rowptr[r] + ch * NNZ_BLK;
+                b.e1 = std::min<int64_t>((int64_t)b.e0 + NNZ_BLK, rowptr[r + 1]);
+                hp.blk.push_back(b);
+                hp.lr.push_back(id);
+            }
+            ++r;
+        } else {
+            const int64_t r0 = r;
+            const int64_t e0 = rowptr[r];
+            while (r < nrows && r - r0 < BS && (int64_t)rowptr[r + 1] - e0 <= NNZ_BLK) ++r;
+            Block b;
+            b.row0 = (int32_t)r0;
+            b.row1 = (int32_t)r;
+            b.e0 = (int32_t)e0;
+            b.e1 = rowptr[r];
+            hp.blk.push_back(b);
+            hp.lr.push_back(-1);
+        }
+    }
+    return hp;
+}
+
+struct DevPartition {
+    DevMem blk, lr, lr_first, lr_nchunk, lr_count, lr_partial;
+    Blocks view{};
+    int upload(const HostPartition &hp) {
+        const size_t nb = hp.blk.size(), nl = hp.lr_first.size();
+        int rc;
+        if ((rc = blk.alloc(std::max<size_t>(nb, 1) * sizeof(Block)))) return rc;
+        if ((rc = lr.alloc(std::max<size_t>(nb, 1) * sizeof(int32_t)))) return rc;
+        if ((rc = lr_first.alloc(std::max<size_t>(nl, 1) * sizeof(int32_t)))) return rc;
+        if ((rc = lr_nchunk.alloc(std::max<size_t>(nl, 1) * sizeof(int32_t)))) return rc;
+        if ((rc = lr_count.alloc(std::max<size_t>(nl, 1) * sizeof(int32_t)))) return rc;
+        if ((rc = lr_partial.alloc(std::max<size_t>(nb, 1) * 4 * sizeof(double)))) return rc;
+        if (nb) {
+            HIPCHK(hipMemcpy(blk.p, hp.blk.data(), nb * sizeof(Block), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(lr.p, hp.lr.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice));
+        }
+        if (nl) {
+            HIPCHK(hipMemcpy(lr_first.p, hp.lr_first.data(), nl * sizeof(int32_t),
+                             hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(lr_nchunk.p, hp.lr_nchunk.data(), nl * sizeof(int32_t),
+                             hipMemcpyHostToDevice));
+        }
+        HIPCHK(hipMemset(lr_count.p, 0, lr_count.bytes));
+        view.blk = blk.as<Block>();
+        view.lr = lr.as<int32_t>();
+        view.lr_first = lr_first.as<int32_t>();
+        view.lr_nchunk = lr_nchunk.as<int32_t>();
+        view.lr_count = lr_count.as<int32_t>();
+        view.lr_partial = lr_partial.as<double>();
+        view.nblk = (int32_t)nb;
+        view.nlr = (int32_t)nl;
+        return QP_OK;
+    }
+};
+
+// copies `count` elements of an input array (host or device) to a host vector
+template <class T>
+int fetch(std::vector<T> &dst, const T *src, int64_t count, int mem_space) {
+    dst.resize((size_t)count);
+    if (count == 0) return QP_OK;
+    if (mem_space == QP_MEM_HOST) {
+        std::memcpy(dst.data(), src, (size_t)count * sizeof(T));
+    } else {
+        HIPCHK(hipMemcpy(dst.data(), src, (size_t)count * sizeof(T), hipMemcpyDeviceToHost));
+    }
+    return QP_OK;
+}
+
+int validate_csr(const char *name, const std::vector<int32_t> &rowptr, int64_t nrows,
+                 int64_t nnz, const std::vector<int32_t> &col, int64_t ncols) {
+    if (rowptr[0] != 0) return fail(QP_ERR_INVALID_ARGUMENT, "%s.row_ptr[0] must be 0", name);
+    for (int64_t i = 0; i < nrows; ++i)
+        if (rowptr[i + 1] < rowptr[i])
+            return fail(QP_ERR_INVALID_ARGUMENT, "%s.row_ptr decreases at row %lld", name,
+                        (long long)i);
+    if (rowptr[nrows] != nnz)
+        return fail(QP_ERR_INVALID_ARGUMENT, "%s.row_ptr[nrows] = %d but nnz = %lld", name,
+                    rowptr[nrows], (long long)nnz);
+    for (int64_t e = 0; e < nnz; ++e)
+        if (col[e] < 0 || col[e] >= ncols)
+            return fail(QP_ERR_INVALID_ARGUMENT, "%s.col_idx[%lld] = %d out of range [0,%lld)",
+                        name, (long long)e, col[e], (long long)ncols);
+    return QP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the handle
+// ---------------------------------------------------------------------------
+struct qp_handle {
+    int64_t n = 0, m = 0;
+    int32_t mem_space = QP_MEM_HOST;
+    int32_t device = 0;
+    qp_settings set{};
+    hipStream_t stream = nullptr;
+
+    // problem data
+    DevMem a_rowptr, a_col, a_val, p_rowptr, p_col, p_val;
+    DevMem c, b, l, u, rt;
+    DevPartition partA, partP;
+    Csr A{}, P{};
+    double norm_A = 0.0, norm_Q = 0.0, c_inf = 0.0, b_inf = 0.0, c_norm2 = 0.0, b_norm2 = 0.0;
+    double dual_bytes = 0.0, primal_bytes = 0.0;  // algorithmic HBM bytes of one launch
+
+    // solver vectors
+    DevMem x, xbar, xt, xmd0, xmd1, xrs, y, ybar, yrs, x0buf, y0buf;
+    DevMem partials_a, partials_p, state, table;
+    Vecs vecs{};
+    int32_t nslotA = 0, nslotP = 0;
+    State *h_state = nullptr;  // pinned ring of status records
+    static constexpr int RING = 8;
+    hipEvent_t ring_ev[RING]{};
+    hipGraphExec_t graph[2]{nullptr, nullptr};
+    int32_t graph_interval = 0;
+    DevSettings graph_ds{};
+
+    // profiling
+    std::vector<hipEvent_t> prof_ev;
+    qp_profile prof{};
+    std::vector<qp_check_info> log;
+
+    // batch mode
+    qpb::BatchData *batch = nullptr;
+
+    ~qp_handle() {
+        for (auto &g : graph)
+            if (g) (void)hipGraphExecDestroy(g);
+        for (auto &e : ring_ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto &e : prof_ev) (void)hipEventDestroy(e);
+        if (h_state) (void)hipHostFree(h_state);
+        qpb::destroy_batch(batch);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+extern "C" {
+
+void qp_default_settings(qp_settings *s) {
+    if (!s) return;
+    std::memset(s, 0, sizeof(*s));
+    s->eps = 1e-6;
+    s->max_iter = 200000;
+    s->time_limit_s = 3600.0;
+    s->check_every = 64;
+    s->restart_mode = QP_RESTART_ADAPTIVE;
+    s->fixed_K = 100;
+    s->beta_sufficient = 0.2;
+    s->beta_necessary = 0.8;
+    s->beta_artificial = 0.36;
+    s->pw_smoothing = 0.2;
+    s->eps_zero = 1e-10;
+    s->step_safety = 0.99;
+    s->norm_A = 0.0;
+    s->norm_Q = 0.0;
+    s->power_iter_max = 1000;
+    s->power_iter_rtol = 1e-7;
+    s->warm_fallback = 1;
+    s->use_graph = 1;
+    s->profile = 0;
+    s->log_checks = 0;
+    s->device = 0;
+}
+
+const char *qp_last_error(void) { return g_err.c_str(); }
+
+int qp_version(void) { return QP_ABI_VERSION; }
+
+}  // extern "C"
+
+namespace {
+
+int check_settings(const qp_settings &s) {
+    if (!(s.eps >= 0.0)) return fail(QP_ERR_INVALID_ARGUMENT, "eps must be >= 0");
+    if (s.check_every <= 0) return fail(QP_ERR_INVALID_ARGUMENT, "check_every must be > 0");
+    if (s.restart_mode < 0 || s.restart_mode > 3)
+        return fail(QP_ERR_INVALID_ARGUMENT, "unknown restart_mode %d", s.restart_mode);
+    if (s.restart_mode == QP_RESTART_FIXED_K && s.fixed_K <= 0)
+        return fail(QP_ERR_INVALID_ARGUMENT, "fixed_K must be > 0");
+    if (s.check_every > 4096 || (s.restart_mode == QP_RESTART_FIXED_K && s.fixed_K > 4096))
+        return fail(QP_ERR_INVALID_ARGUMENT, "evaluation interval above 4096 is not supported");
+    if (!(s.step_safety > 0.0)) return fail(QP_ERR_INVALID_ARGUMENT, "step_safety must be > 0");
+    return QP_OK;
+}
+
+// power iteration for ||A||_2 (Rayleigh quotient of A'A) and ||Q||_2
+int estimate_norms(qp_handle *h) {
+    const int64_t n = h->n, m = h->m;
+    hipStream_t s = h->stream;
+    DevMem v, w, z, parts;
+    const int np_n = dot_nparts(n), np_m = dot_nparts(std::max<int64_t>(m, 1));
+    int rc;
+    if ((rc = v.alloc(n * 8)) || (rc = z.alloc(n * 8)) || (rc = w.alloc(std::max<int64_t>(m, 1) * 8)) ||
+        (rc = parts.alloc(1024 * 8)))
+        return rc;
+    std::vector<double> hp(1024);
+    auto dot = [&](const double *a, const double *b, int64_t len, int np, double *out) -> int {
+        launch_dot_partials(s, a, b, len, parts.as<double>(), np);
+        HIPCHK(hipMemcpyAsync(hp.data(), parts.p, np * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double acc = 0.0;
+        for (int i = 0; i < np; ++i) acc = acc + hp[i];
+        *out = acc;
+        return QP_OK;
+    };
+    const int maxit = h->set.power_iter_max;
+    const double rtol = h->set.power_iter_rtol;
+    if (!(h->set.norm_A > 0.0)) {
+        double lam = 0.0;
+        const int64_t annz = h->partA.view.nblk ? 1 : 0;
+        if (m > 0 && annz) {
+            launch_fill(s, v.as<double>(), n, 1.0 / std::sqrt((double)n));
+            double lam_prev = 0.0;
+            for (int it = 1; it <= maxit; ++it) {
+                launch_spmv_plain(s, h->partA.view, h->A, v.as<double>(), nullptr, n,
+                                  w.as<double>(), 1.0);
+                if ((rc = dot(w.as<double>(), w.as<double>(), m, np_m, &lam))) return rc;
+                launch_spmv_plain(s, h->partP.view, h->P, nullptr, w.as<double>(), n,
+                                  z.as<double>(), -1.0);
+                double nz2;
+                if ((rc = dot(z.as<double>(), z.as<double>(), n, np_n, &nz2))) return rc;
+                const double nz = std::sqrt(nz2);
+                if (nz == 0.0) break;
+                launch_div(s, v.as<double>(), z.as<double>(), n, nz);
+                if (it > 1 && std::fabs(lam - lam_prev) <= rtol * lam) break;
+                lam_prev = lam;
+            }
+        }
+        h->norm_A = std::sqrt(lam);
+    } else {
+        h->norm_A = h->set.norm_A;
+    }
+    if (!(h->set.norm_Q > 0.0)) {
+        double lam = 0.0;
+        launch_fill(s, v.as<double>(), n, 1.0 / std::sqrt((double)n));
+        double lam_prev = 0.0;
+        for (int it = 1; it <= maxit; ++it) {
+            launch_spmv_plain(s, h->partP.view, h->P, v.as<double>(), nullptr, n, z.as<double>(),
+                              1.0);
+            if ((rc = dot(v.as<double>(), z.as<double>(), n, np_n, &lam))) return rc;
+            double nw2;
+            if ((rc = dot(z.as<double>(), z.as<double>(), n, np_n, &nw2))) return rc;
+            const double nw = std::sqrt(nw2);
+            if (nw == 0.0) break;
+            launch_div(s, v.as<double>(), z.as<double>(), n, nw);
+            if (it > 1 && std::fabs(lam - lam_prev) <= rtol * std::fabs(lam)) break;
+            lam_prev = lam;
+        }
+        h->norm_Q = std::fabs(lam);
+    } else {
+        h->norm_Q = h->set.norm_Q;
+    }
+    return QP_OK;
+}
+
+int set_vectors_host_stats(qp_handle *h, const std::vector<double> &c, const std::vector<double> &b) {
+    double cn = 0.0, bn = 0.0, ci = 0.0, bi = 0.0;
+    for (double v : c) {
+        cn += v * v;
+        if (std::fabs(v) > ci) ci = std::fabs(v);
+    }
+    for (double v : b) {
+        bn += v * v;
+        if (std::fabs(v) > bi) bi = std::fabs(v);
+    }
+    h->c_norm2 = std::sqrt(cn);
+    h->b_norm2 = std::sqrt(bn);
+    h->c_inf = ci;
+    h->b_inf = bi;
+    return QP_OK;
+}
+
+struct HostProblem {
+    std::vector<int32_t> qr, qc, ar, ac;
+    std::vector<double> qv, av, c, b, l, u;
+    std::vector<uint8_t> rt;
+};
+
+// Copies the problem to host vectors and validates it (no device work for host input).
+int gather_single(const qp_problem_desc *d, HostProblem &hp) {
+    const int64_t n = d->n, m = d->m;
+    const int ms = d->mem_space;
+    auto &qr = hp.qr, &qc = hp.qc, &ar = hp.ar, &ac = hp.ac;
+    auto &qv = hp.qv, &av = hp.av, &c = hp.c, &b = hp.b, &l = hp.l, &u = hp.u;
+    auto &rt = hp.rt;
+    int rc;
+    if ((rc = fetch(qr, d->Q.row_ptr, n + 1, ms))) return rc;
+    if (qr[n] != d->Q.nnz || d->Q.nnz < 0)
+        return fail(QP_ERR_INVALID_ARGUMENT, "Q.nnz (%lld) disagrees with Q.row_ptr[n] (%d)",
+                    (long long)d->Q.nnz, qr[n]);
+    if ((rc = fetch(qc, d->Q.col_idx, d->Q.nnz, ms)) || (rc = fetch(qv, d->Q.val, d->Q.nnz, ms)))
+        return rc;
+    if ((rc = validate_csr("Q", qr, n, d->Q.nnz, qc, n))) return rc;
+    if (m > 0) {
+        if (!d->A.row_ptr || !d->b)
+            return fail(QP_ERR_INVALID_ARGUMENT, "A.row_ptr and b are required when m > 0");
+        if ((rc = fetch(ar, d->A.row_ptr, m + 1, ms))) return rc;
+        if (ar[m] != d->A.nnz || d->A.nnz < 0)
+            return fail(QP_ERR_INVALID_ARGUMENT, "A.nnz (%lld) disagrees with A.row_ptr[m] (%d)",
+                        (long long)d->A.nnz, ar[m]);
+        if ((rc = fetch(ac, d->A.col_idx, d->A.nnz, ms)) || (rc = fetch(av, d->A.val, d->A.nnz, ms)))
+            return rc;
+        if ((rc = validate_csr("A", ar, m, d->A.nnz, ac, n))) return rc;
+        if ((rc = fetch(b, d->b, m, ms))) return rc;
+        if (d->row_type) {
+            if ((rc = fetch(rt, d->row_type, m, ms))) return rc;
+            for (int64_t i = 0; i < m; ++i)
+                if (rt[i] > 1)
+                    return fail(QP_ERR_INVALID_ARGUMENT, "row_type[%lld] = %d is not 0 (EQ) or 1 (GE)",
+                                (long long)i, rt[i]);
+        } else {
+            rt.assign(m, 0);
+        }
+    } else {
+        ar.assign(1, 0);
+    }
+    if (!d->c) return fail(QP_ERR_INVALID_ARGUMENT, "c is required");
+    if ((rc = fetch(c, d->c, n, ms))) return rc;
+    if (d->l) {
+        if ((rc = fetch(l, d->l, n, ms))) return rc;
+    } else {
+        l.assign(n, -INFINITY);
+    }
+    if (d->u) {
+        if ((rc = fetch(u, d->u, n, ms))) return rc;
+    } else {
+        u.assign(n, INFINITY);
+    }
+    for (int64_t j = 0; j < n; ++j)
+        if (!(l[j] <= u[j]) || l[j] == INFINITY || u[j] == -INFINITY)
+            return fail(QP_ERR_INVALID_ARGUMENT, "invalid bounds at variable %lld: [%g, %g]",
+                        (long long)j, l[j], u[j]);
+    const int64_t pnnz = d->Q.nnz + (m > 0 ? d->A.nnz : 0);
+    if (pnnz >= ((int64_t)1 << 31) || n + m >= ((int64_t)1 << 31))
+        return fail(QP_ERR_INVALID_ARGUMENT, "problem exceeds int32 indexing");
+    return QP_OK;
+}
+
+int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
+    const int64_t n = d->n, m = d->m;
+    const auto &qr = hp.qr, &qc = hp.qc, &ar = hp.ar, &ac = hp.ac;
+    const auto &qv = hp.qv, &av = hp.av, &c = hp.c, &b = hp.b, &l = hp.l, &u = hp.u;
+    const auto &rt = hp.rt;
+    int rc;
+    const int64_t pnnz = d->Q.nnz + (m > 0 ? d->A.nnz : 0);
+
+    // P = [Q | -A'] ; the A' entries of row j follow the Q entries, ordered by A's row index
+    std::vector<int32_t> pr(n + 1, 0), pc((size_t)pnnz);
+    std::vector<double> pv((size_t)pnnz);
+    std::vector<int64_t> acount(n, 0);
+    for (int64_t e = 0; e < (m > 0 ? d->A.nnz : 0); ++e) acount[ac[e]]++;
+    for (int64_t j = 0; j < n; ++j) pr[j + 1] = (int32_t)(pr[j] + (qr[j + 1] - qr[j]) + acount[j]);
+    std::vector<int64_t> next(n);
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t pos = pr[j];
+        for (int64_t e = qr[j]; e < qr[j + 1]; ++e, ++pos) {
+            pc[pos] = qc[e];
+            pv[pos] = qv[e];
+        }
+        next[j] = pos;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t e = ar[i]; e < ar[i + 1]; ++e) {
+            const int64_t pos = next[ac[e]]++;
+            pc[pos] = (int32_t)(n + i);
+            pv[pos] = -av[e];
+        }
+
+    auto up = [&](DevMem &dm, const void *src, size_t bytes) -> int {
+        int r2 = dm.alloc(std::max<size_t>(bytes, 8));
+        if (r2) return r2;
+        if (bytes) HIPCHK(hipMemcpy(dm.p, src, bytes, hipMemcpyHostToDevice));
+        return QP_OK;
+    };
+    if ((rc = up(h->a_rowptr, ar.data(), ar.size() * 4)) || (rc = up(h->a_col, ac.data(), ac.size() * 4)) ||
+        (rc = up(h->a_val, av.data(), av.size() * 8)) || (rc = up(h->p_rowptr, pr.data(), pr.size() * 4)) ||
+        (rc = up(h->p_col, pc.data(), pc.size() * 4)) || (rc = up(h->p_val, pv.data(), pv.size() * 8)) ||
+        (rc = up(h->c, c.data(), n * 8)) || (rc = up(h->b, b.data(), b.size() * 8)) ||
+        (rc = up(h->l, l.data(), n * 8)) || (rc = up(h->u, u.data(), n * 8)) ||
+        (rc = up(h->rt, rt.data(), rt.size())))
+        return rc;
+    h->A = Csr{h->a_rowptr.as<int32_t>(), h->a_col.as<int32_t>(), h->a_val.as<double>(), m};
+    h->P = Csr{h->p_rowptr.as<int32_t>(), h->p_col.as<int32_t>(), h->p_val.as<double>(), n};
+    HostPartition hpA = partition_rows(ar.data(), m), hpP = partition_rows(pr.data(), n);
+    {
+        // Algorithmic bytes of one launch: matrix values (8 B) + column indices (4 B) per
+        // nonzero, row pointers (4 B per row), every distinct gathered vector entry once
+        // (8 B), and the per-row vector traffic of the fused epilogue:
+        //   dual:   read y, y-bar, b (24 B) + row type (1 B), write y, y-bar (16 B)
+        //   primal: read x, x-bar, c, l, u (40 B), write x, x-bar, x~, x_md (32 B)
+        std::vector<uint8_t> seen((size_t)(n + m), 0);
+        int64_t gA = 0, gP = 0;
+        for (int64_t e = 0; e < (m > 0 ? d->A.nnz : 0); ++e)
+            if (!seen[ac[e]]) { seen[ac[e]] = 1; ++gA; }
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int64_t e = 0; e < pnnz; ++e)
+            if (!seen[pc[e]]) { seen[pc[e]] = 1; ++gP; }
+        const double annz = (double)(m > 0 ? d->A.nnz : 0);
+        h->dual_bytes = m > 0 ? 12.0 * annz + 4.0 * (double)(m + 1) + 8.0 * (double)gA +
+                                    41.0 * (double)m : 0.0;
+        h->primal_bytes = 12.0 * (double)pnnz + 4.0 * (double)(n + 1) + 8.0 * (double)gP +
+                          72.0 * (double)n;
+    }
+    if ((rc = h->partA.upload(hpA)) || (rc = h->partP.upload(hpP))) return rc;
+    set_vectors_host_stats(h, c, b);
+
+    // solver vectors
+    const size_t nb = (size_t)n * 8, mb = (size_t)std::max<int64_t>(m, 1) * 8;
+    if ((rc = h->x.alloc(nb)) || (rc = h->xbar.alloc(nb)) || (rc = h->xt.alloc(nb)) ||
+        (rc = h->xmd0.alloc(nb)) || (rc = h->xmd1.alloc(nb)) || (rc = h->xrs.alloc(nb)) ||
+        (rc = h->y.alloc(mb)) || (rc = h->ybar.alloc(mb)) || (rc = h->yrs.alloc(mb)) ||
+        (rc = h->x0buf.alloc(nb)) || (rc = h->y0buf.alloc(mb)))
+        return rc;
+    h->nslotA = h->partA.view.nblk + h->partA.view.nlr;
+    h->nslotP = h->partP.view.nblk + h->partP.view.nlr;
+    if ((rc = h->partials_a.alloc((size_t)std::max(h->nslotA, 1) * RA_NV * 8)) ||
+        (rc = h->partials_p.alloc((size_t)std::max(h->nslotP, 1) * RP_NV * 8)) ||
+        (rc = h->state.alloc(sizeof(State))) || (rc = h->table.alloc(4096 * sizeof(Step))))
+        return rc;
+    Vecs &v = h->vecs;
+    v.x = h->x.as<double>();
+    v.xbar = h->xbar.as<double>();
+    v.xt = h->xt.as<double>();
+    v.xmd[0] = h->xmd0.as<double>();
+    v.xmd[1] = h->xmd1.as<double>();
+    v.xrs = h->xrs.as<double>();
+    v.y = h->y.as<double>();
+    v.ybar = h->ybar.as<double>();
+    v.yrs = h->yrs.as<double>();
+    v.c = h->c.as<double>();
+    v.b = h->b.as<double>();
+    v.l = h->l.as<double>();
+    v.u = h->u.as<double>();
+    v.rt = h->rt.as<uint8_t>();
+    return QP_OK;
+}
+
+DevSettings dev_settings(const qp_handle *h) {
+    DevSettings ds;
+    std::memset(&ds, 0, sizeof(ds));  // padding bytes take part in the graph-cache comparison
+    const qp_settings &s = h->set;
+    ds.eps = s.eps;
+    ds.beta_sufficient = s.beta_sufficient;
+    ds.beta_necessary = s.beta_necessary;
+    ds.beta_artificial = s.beta_artificial;
+    ds.pw_smoothing = s.pw_smoothing;
+    ds.eps_zero = s.eps_zero;
+    ds.step_safety = s.step_safety;
+    ds.norm_A = h->norm_A;
+    ds.norm_Q = h->norm_Q;
+    ds.b_inf = h->b_inf;
+    ds.c_inf = h->c_inf;
+    ds.max_iter = s.max_iter;
+    ds.restart_mode = s.restart_mode;
+    ds.fixed_K = s.fixed_K;
+    ds.interval = s.restart_mode == QP_RESTART_FIXED_K ? s.fixed_K : s.check_every;
+    return ds;
+}
+
+// one interval of `len` iterations starting with x_md in buffer md_in
+void enqueue_interval(qp_handle *h, const DevSettings &ds, int md_in, int len, bool timed) {
+    hipStream_t s = h->stream;
+    const Step *tab = h->table.as<Step>();
+    State *st = h->state.as<State>();
+    int md = md_in;
+    for (int j = 0; j < len; ++j) {
+        if (timed) (void)hipEventRecord(h->prof_ev[4 * j + 0], s);
+        launch_dual(s, h->partA.view, h->A, h->vecs, tab + j, st);
+        if (timed) (void)hipEventRecord(h->prof_ev[4 * j + 1], s);
+        launch_primal(s, h->partP.view, h->P, h->vecs, md, tab + j, st, h->n);
+        if (timed) (void)hipEventRecord(h->prof_ev[4 * j + 2], s);
+        md ^= 1;
+    }
+    launch_kkt_rows(s, h->partA.view, h->A, h->vecs, h->partials_a.as<double>(), st);
+    launch_kkt_cols(s, h->partP.view, h->P, h->vecs, h->partials_p.as<double>(), st, h->n);
+    launch_decide(s, DECIDE_CHECK, h->partials_a.as<double>(), h->nslotA,
+                  h->partials_p.as<double>(), h->nslotP, st, h->table.as<Step>(), ds, len);
+    launch_apply(s, h->vecs, md, st, h->n, h->m);
+}
+
+int get_graph(qp_handle *h, const DevSettings &ds, int md_in, hipGraphExec_t *out) {
+    if (h->graph_interval != ds.interval || std::memcmp(&h->graph_ds, &ds, sizeof(ds)) != 0) {
+        for (auto &g : h->graph)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+        h->graph_interval = ds.interval;
+        h->graph_ds = ds;  // captured kernel arguments are frozen: re-capture on any change
+    }
+    if (!h->graph[md_in]) {
+        hipGraph_t g;
+        HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_interval(h, ds, md_in, ds.interval, false);
+        HIPCHK(hipStreamEndCapture(h->stream, &g));
+        hipError_t e = hipGraphInstantiate(&h->graph[md_in], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess)
+            return fail(QP_ERR_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    *out = h->graph[md_in];
+    return QP_OK;
+}
+
+void fill_result(const qp_handle *h, const State &S, double t, qp_result *res) {
+    std::memset(res, 0, sizeof(*res));
+    res->status = S.status;
+    res->used_warm_start = S.used_warm;
+    res->iterations = S.total;
+    res->restarts = S.restarts;
+    res->kkt_evals = S.kkt_evals;
+    const double *k = S.kkt[S.cand ? 1 : 0];
+    res->r_primal = k[0];
+    res->r_dual = k[1];
+    res->r_gap = k[2];
+    res->rel_kkt = k[3];
+    res->primal_obj = k[4];
+    res->dual_obj = k[5];
+    res->omega = S.omega;
+    res->norm_A = h->norm_A;
+    res->norm_Q = h->norm_Q;
+    res->solve_time_s = t;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qp_create(const qp_problem_desc *d, const qp_settings *settings, qp_handle **out) {
+    if (!d || !out) return fail(QP_ERR_INVALID_ARGUMENT, "desc and out must be non-null");
+    *out = nullptr;
+    qp_settings s;
+    if (settings) s = *settings;
+    else qp_default_settings(&s);
+    int rc;
+    if ((rc = check_settings(s))) return rc;
+    if (d->n <= 0) return fail(QP_ERR_INVALID_ARGUMENT, "n must be positive");
+    if (d->m < 0) return fail(QP_ERR_INVALID_ARGUMENT, "m must be >= 0");
+    if (d->mem_space != QP_MEM_HOST && d->mem_space != QP_MEM_DEVICE)
+        return fail(QP_ERR_INVALID_ARGUMENT, "unknown mem_space %d", d->mem_space);
+    if (!d->Q.row_ptr || (d->Q.nnz > 0 && (!d->Q.col_idx || !d->Q.val)))
+        return fail(QP_ERR_INVALID_ARGUMENT, "Q arrays are required");
+    if (d->num_instances < 1) return fail(QP_ERR_INVALID_ARGUMENT, "num_instances must be >= 1");
+    HostProblem hp;
+    if (d->num_instances == 1 && d->mem_space == QP_MEM_HOST)
+        if ((rc = gather_single(d, hp))) return rc;  // validation before any device work
+    HIPCHK(hipSetDevice(s.device));
+    qp_handle *h = new qp_handle();
+    h->n = d->n;
+    h->m = d->m;
+    h->mem_space = d->mem_space;
+    h->device = s.device;
+    h->set = s;
+    hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(QP_ERR_DEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+    }
+    if (d->stream) {
+        // the caller's arrays are ordered on its stream: wait for them
+        e = hipStreamSynchronize((hipStream_t)d->stream);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(QP_ERR_DEVICE, "caller stream: %s", hipGetErrorString(e));
+        }
+    }
+    if (d->num_instances > 1) {
+        rc = qpb::create_batch(d, &h->set, &h->batch);
+    } else {
+        if (d->mem_space == QP_MEM_DEVICE) rc = gather_single(d, hp);
+        if (!rc) rc = create_single(d, h, hp);
+        if (!rc) rc = estimate_norms(h);
+        if (!rc && !(h->norm_A > 0.0) && !(h->norm_Q > 0.0))
+            rc = fail(QP_ERR_INVALID_ARGUMENT, "both ||A|| and ||Q|| are zero: nothing to solve");
+        if (!rc) {
+            e = hipHostMalloc((void **)&h->h_state, sizeof(State) * qp_handle::RING, 0);
+            if (e != hipSuccess) rc = fail(QP_ERR_OUT_OF_MEMORY, "hipHostMalloc failed");
+            for (int i = 0; !rc && i < qp_handle::RING; ++i)
+                if (hipEventCreateWithFlags(&h->ring_ev[i], hipEventDisableTiming) != hipSuccess)
+                    rc = fail(QP_ERR_DEVICE, "hipEventCreate failed");
+        }
+    }
+    if (!rc) {
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) rc = fail(QP_ERR_DEVICE, "create: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    g_err.clear();
+    return QP_OK;
+}
+
+void qp_free(qp_handle *h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+int qp_get_norms(qp_handle *h, double *norm_A, double *norm_Q) {
+    if (!h) return fail(QP_ERR_INVALID_ARGUMENT, "null handle");
+    if (h->batch) return qpb::batch_norms(h->batch, norm_A, norm_Q);
+    if (norm_A) *norm_A = h->norm_A;
+    if (norm_Q) *norm_Q = h->norm_Q;
+    return QP_OK;
+}
+
+int qp_update_vectors(qp_handle *h, const double *c, const double *b) {
+    if (!h) return fail(QP_ERR_INVALID_ARGUMENT, "null handle");
+    HIPCHK(hipSetDevice(h->device));
+    if (h->batch) return qpb::batch_update_vectors(h->batch, c, b, h->mem_space);
+    const hipMemcpyKind kind = h->mem_space == QP_MEM_HOST ? hipMemcpyHostToDevice
+                                                           : hipMemcpyDeviceToDevice;
+    if (c) HIPCHK(hipMemcpy(h->c.p, c, h->n * 8, kind));
+    if (b && h->m) HIPCHK(hipMemcpy(h->b.p, b, h->m * 8, kind));
+    std::vector<double> hc(h->n), hb(h->m);
+    HIPCHK(hipMemcpy(hc.data(), h->c.p, h->n * 8, hipMemcpyDeviceToHost));
+    if (h->m) HIPCHK(hipMemcpy(hb.data(), h->b.p, h->m * 8, hipMemcpyDeviceToHost));
+    return set_vectors_host_stats(h, hc, hb);
+}
+
+int qp_get_check_log(qp_handle *h, qp_check_info *buf, int64_t cap, int64_t *len) {
+    if (!h) return fail(QP_ERR_INVALID_ARGUMENT, "null handle");
+    const int64_t k = std::min<int64_t>(cap, (int64_t)h->log.size());
+    if (buf && k > 0) std::memcpy(buf, h->log.data(), (size_t)k * sizeof(qp_check_info));
+    if (len) *len = (int64_t)h->log.size();
+    return QP_OK;
+}
+
+int qp_get_profile(qp_handle *h, qp_profile *out) {
+    if (!h || !out) return fail(QP_ERR_INVALID_ARGUMENT, "null argument");
+    *out = h->prof;
+    return QP_OK;
+}
+
+int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_out,
+             double *y_out) {
+    if (!h || !res) return fail(QP_ERR_INVALID_ARGUMENT, "null handle or result");
+    if (h->batch) return fail(QP_ERR_BATCH_MISMATCH, "qp_solve on a batch handle: use qp_batch_solve");
+    HIPCHK(hipSetDevice(h->device));
+    const double t0 = now_s();
+    const int64_t n = h->n, m = h->m;
+    hipStream_t s = h->stream;
+    DevSettings ds = dev_settings(h);
+    const int L = ds.interval;
+    const bool profile = h->set.profile != 0;
+    const bool use_graph = h->set.use_graph != 0 && !profile;
+    State *st = h->state.as<State>();
+    h->log.clear();
+    h->prof = qp_profile{};
+    h->prof.dual_bytes = 0.0;
+    if (profile && (int)h->prof_ev.size() < 4 * L) {
+        for (auto &e : h->prof_ev) (void)hipEventDestroy(e);
+        h->prof_ev.assign(4 * L, nullptr);
+        for (auto &e : h->prof_ev) HIPCHK(hipEventCreate(&e));
+    }
+
+    // initial primal weight (Sec. 6 InitializePrimalWeight) unless given
+    double omega = (ws && ws->omega0 > 0.0) ? ws->omega0
+                   : (h->c_norm2 > h->set.eps_zero && h->b_norm2 > h->set.eps_zero)
+                       ? h->c_norm2 / h->b_norm2
+                       : 1.0;
+    const double *x0 = nullptr, *y0 = nullptr;
+    if (ws && (ws->x0 || ws->y0)) {
+        const hipMemcpyKind kind = h->mem_space == QP_MEM_HOST ? hipMemcpyHostToDevice
+                                                               : hipMemcpyDeviceToDevice;
+        if (ws->x0) {
+            HIPCHK(hipMemcpyAsync(h->x0buf.p, ws->x0, n * 8, kind, s));
+            x0 = h->x0buf.as<double>();
+        }
+        if (ws->y0 && m) {
+            HIPCHK(hipMemcpyAsync(h->y0buf.p, ws->y0, m * 8, kind, s));
+            y0 = h->y0buf.as<double>();
+        }
+    }
+    const bool warm = ws && (ws->x0 || ws->y0);
+    launch_state_reset(s, st, omega, ds.max_iter);
+    if (warm && h->set.warm_fallback) {
+        launch_init(s, h->vecs, x0, y0, n, m, 1);
+        launch_kkt_rows(s, h->partA.view, h->A, h->vecs, h->partials_a.as<double>(), st);
+        launch_kkt_cols(s, h->partP.view, h->P, h->vecs, h->partials_p.as<double>(), st, n);
+        launch_decide(s, DECIDE_FALLBACK, h->partials_a.as<double>(), h->nslotA,
+                      h->partials_p.as<double>(), h->nslotP, st, h->table.as<Step>(), ds, 0);
+        launch_fallback_apply(s, h->vecs, st, n, m);
+    } else {
+        launch_init(s, h->vecs, x0, y0, n, m, 0);
+        if (warm) {
+            // warm start taken unconditionally
+            State one{};
+            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(hipMemcpy(&one, st, sizeof(State), hipMemcpyDeviceToHost));
+            one.used_warm = 1;
+            HIPCHK(hipMemcpy(st, &one, sizeof(State), hipMemcpyHostToDevice));
+        }
+    }
+    launch_kkt_rows(s, h->partA.view, h->A, h->vecs, h->partials_a.as<double>(), st);
+    launch_kkt_cols(s, h->partP.view, h->P, h->vecs, h->partials_p.as<double>(), st, n);
+    launch_decide(s, DECIDE_INIT, h->partials_a.as<double>(), h->nslotA,
+                  h->partials_p.as<double>(), h->nslotP, st, h->table.as<Step>(), ds, 0);
+    HIPCHK(hipMemcpyAsync(&h->h_state[0], st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    State last = h->h_state[0];
+
+    int64_t enqueued = 0;
+    int md = 0;
+    int slot = 0;
+    std::deque<std::pair<int, int>> inflight;  // (ring slot, interval length)
+    bool stop = last.done != 0;
+    bool time_up = false;
+    int32_t seen_checks = 0;
+    auto process = [&](int sl, int len) -> int {
+        HIPCHK(hipEventSynchronize(h->ring_ev[sl]));
+        const State &S = h->h_state[sl];
+        if (profile) {
+            for (int j = 0; j < len; ++j) {
+                float a = 0.f, b = 0.f;
+                HIPCHK(hipEventElapsedTime(&a, h->prof_ev[4 * j + 0], h->prof_ev[4 * j + 1]));
+                HIPCHK(hipEventElapsedTime(&b, h->prof_ev[4 * j + 1], h->prof_ev[4 * j + 2]));
+                h->prof.dual_ms += a;
+                h->prof.primal_ms += b;
+            }
+            if (m > 0) h->prof.dual_launches += len;
+            h->prof.primal_launches += len;
+        }
+        if (S.checks > seen_checks) {
+            seen_checks = S.checks;
+            if (h->set.log_checks) {
+                qp_check_info ci;
+                ci.total = S.total;
+                ci.k = S.k;
+                ci.r_cur = S.r_cur;
+                ci.r_avg = S.r_avg;
+                ci.candidate = S.cand;
+                ci.restarted = S.restart_flag;
+                ci.omega = S.omega;
+                h->log.push_back(ci);
+            }
+        }
+        last = S;
+        if (S.done) stop = true;
+        if (h->set.time_limit_s > 0.0 && now_s() - t0 >= h->set.time_limit_s) time_up = true;
+        return QP_OK;
+    };
+    int rc;
+    while (!stop && !time_up && enqueued < ds.max_iter) {
+        const int len = (int)std::min<int64_t>(L, ds.max_iter - enqueued);
+        if (use_graph && len == L) {
+            hipGraphExec_t g;
+            if ((rc = get_graph(h, ds, md, &g))) return rc;
+            HIPCHK(hipGraphLaunch(g, s));
+        } else {
+            enqueue_interval(h, ds, md, len, profile);
+        }
+        md = (md + len) & 1;
+        enqueued += len;
+        HIPCHK(hipMemcpyAsync(&h->h_state[slot], st, sizeof(State), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(h->ring_ev[slot], s));
+        inflight.emplace_back(slot, len);
+        slot = (slot + 1) % qp_handle::RING;
+        // profiling reuses one event set per interval: drain before the next one
+        const size_t depth = profile ? 0 : 1;
+        while (inflight.size() > depth) {
+            auto [sl, ln] = inflight.front();
+            inflight.pop_front();
+            if ((rc = process(sl, ln))) return rc;
+        }
+    }
+    while (!inflight.empty()) {
+        auto [sl, ln] = inflight.front();
+        inflight.pop_front();
+        if ((rc = process(sl, ln))) return rc;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (!last.done) last.status = time_up ? QP_TIME_LIMIT : QP_ITERATION_LIMIT;
+    if (profile) {
+        h->prof.dual_bytes = h->dual_bytes;
+        h->prof.primal_bytes = h->primal_bytes;
+    }
+    // outputs: the candidate of the last evaluation
+    const hipMemcpyKind kind = h->mem_space == QP_MEM_HOST ? hipMemcpyDeviceToHost
+                                                           : hipMemcpyDeviceToDevice;
+    const double *xs = last.cand ? h->vecs.xbar : h->vecs.x;
+    const double *ys = last.cand ? h->vecs.ybar : h->vecs.y;
+    if (x_out) HIPCHK(hipMemcpy(x_out, xs, n * 8, kind));
+    if (y_out && m) HIPCHK(hipMemcpy(y_out, ys, m * 8, kind));
+    fill_result(h, last, now_s() - t0, res);
+    g_err.clear();
+    return QP_OK;
+}
+
+int qp_batch_solve(qp_handle *h, const qp_warm_start *ws_array, qp_result *res_array,
+                   double *x_out, double *y_out) {
+    if (!h || !res_array) return fail(QP_ERR_INVALID_ARGUMENT, "null handle or result array");
+    if (!h->batch) return fail(QP_ERR_BATCH_MISMATCH, "qp_batch_solve needs a batch handle");
+    HIPCHK(hipSetDevice(h->device));
+    return qpb::batch_solve(h->batch, &h->set, h->mem_space, ws_array, res_array, x_out, y_out);
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// qp_internal.h -- device data layouts shared by the HIP kernels and the host
+// orchestration of the rAPDHG solver.  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qpk {
+
+// Row-kernel geometry: one workgroup of BS threads stages up to NNZ_BLK
+// products in LDS; rows of a block never exceed BS; a row longer than NNZ_BLK
+// is split into chunks whose partial sums are combined by the last chunk to
+// arrive (deterministic: partials are summed in chunk order).
+constexpr int BS = 256;
+constexpr int NNZ_BLK = 2048;
+constexpr int EPT = NNZ_BLK / BS;
+
+struct Block {
+    int32_t row0, row1;  // rows [row0, row1)
+    int32_t e0, e1;      // nnz range [e0, e1) staged by this workgroup
+};
+
+// Row partition of one CSR matrix (device pointers).
+struct Blocks {
+    const Block *blk;
+    const int32_t *lr;        // [nblk] long-row id of a chunk block, -1 otherwise
+    const int32_t *lr_first;  // [nlr] first block of each long row
+    const int32_t *lr_nchunk; // [nlr]
+    int32_t *lr_count;        // [nlr] arrival counters, zero between launches
+    double *lr_partial;       // [nblk * 4] chunk partial sums
+    int32_t nblk, nlr;
+};
+
+struct Csr {
+    const int32_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    int64_t nrows;
+};
+
+// Per-iteration scalars of one inner index k, written by the decision kernel.
+struct Step {
+    double p;          // primal step  (Sec. 6: eta / omega; Thm 1: eta_k)
+    double d;          // dual step    (Sec. 6: eta * omega; Thm 1: tau_k)
+    double w;          // 1 / beta_k = 2 / (k + 2)
+    double theta_next; // theta_{k+1} = (k + 1) / (k + 2)
+    double w_next;     // 1 / beta_{k+1}
+    double pad[3];
+};
+
+// Indices of the per-point KKT quantities in the block partials.
+enum : int {
+    RA_RES0 = 0, RA_RES1, RA_AX0, RA_AX1, RA_BY0, RA_BY1, RA_DY0, RA_DY1, RA_NV
+};
+enum : int {
+    RP_DRES0 = 0, RP_DRES1, RP_QX0, RP_QX1, RP_ATY0, RP_ATY1, RP_XQX0, RP_XQX1, RP_CX0, RP_CX1,
+    RP_BND0, RP_BND1, RP_DX0, RP_DX1, RP_NV
+};
+
+struct State {
+    double omega, r0, prev_cand, s_last;
+    double r_cur, r_avg;
+    double kkt[2][6];  // per point: r_primal, r_dual, r_gap, rel_kkt, primal_obj, dual_obj
+    int64_t total, k, restarts, kkt_evals;
+    int32_t done, status, cand, restart_flag;
+    int32_t used_warm, checks, pad0, pad1;
+};
+
+struct DevSettings {
+    double eps, beta_sufficient, beta_necessary, beta_artificial, pw_smoothing, eps_zero;
+    double step_safety, norm_A, norm_Q, b_inf, c_inf;
+    int64_t max_iter;
+    int32_t restart_mode, fixed_K, interval;
+};
+
+enum : int { DECIDE_INIT = 0, DECIDE_CHECK = 1, DECIDE_FALLBACK = 2 };
+enum : int { MODE_ADAPTIVE = 0, MODE_FIXED_K = 1, MODE_HALVING = 2, MODE_NONE = 3 };
+enum : int { ST_OPTIMAL = 0, ST_ITER_LIMIT = 1, ST_TIME_LIMIT = 2, ST_NUMERICAL = 3 };
+
+// Vectors of a single-instance solve (device pointers).
+struct Vecs {
+    double *x, *xbar, *xt, *xmd[2], *xrs;  // primal: iterate, average, extrapolated
+                                          // point, x_md ping-pong, last restart point
+    double *y, *ybar, *yrs;               // dual
+    const double *c, *b, *l, *u;
+    const uint8_t *rt;
+};
+
+// ---- launchers (qp_kernels.hip) ----
+void launch_dual(hipStream_t s, const Blocks &bk, const Csr &A, const Vecs &v, const Step *step,
+                 const State *st);
+void launch_primal(hipStream_t s, const Blocks &bk, const Csr &P, const Vecs &v, int md_in,
+                   const Step *step, const State *st, int64_t n);
+void launch_kkt_rows(hipStream_t s, const Blocks &bk, const Csr &A, const Vecs &v,
+                     double *partials, const State *st);
+void launch_kkt_cols(hipStream_t s, const Blocks &bk, const Csr &P, const Vecs &v,
+                     double *partials, const State *st, int64_t n);
+void launch_decide(hipStream_t s, int mode, const double *partA, int32_t nslotA,
+                   const double *partP, int32_t nslotP, State *st, Step *table,
+                   const DevSettings &ds, int32_t len);
+void launch_apply(hipStream_t s, const Vecs &v, int md_out, const State *st, int64_t n,
+                  int64_t m);
+void launch_init(hipStream_t s, const Vecs &v, const double *x0, const double *y0, int64_t n,
+                 int64_t m, int pair_with_cold);
+void launch_fallback_apply(hipStream_t s, const Vecs &v, const State *st, int64_t n, int64_t m);
+void launch_state_reset(hipStream_t s, State *st, double omega, int64_t max_iter);
+
+// power iteration helpers: y = M_1 x + sign2 * M_2 x2 where M_1 holds the
+// entries with col < split and M_2 those with col >= split (x or x2 may be null)
+void launch_spmv_plain(hipStream_t s, const Blocks &bk, const Csr &M, const double *x,
+                       const double *x2, int64_t split, double *y, double sign2);
+// partials[i] = sum over the i-th contiguous chunk of a .* b (fixed order)
+void launch_dot_partials(hipStream_t s, const double *a, const double *b, int64_t n,
+                         double *partials, int32_t nparts);
+void launch_div(hipStream_t s, double *dst, const double *src, int64_t n, double den);
+void launch_fill(hipStream_t s, double *dst, int64_t n, double value);
+int dot_nparts(int64_t n);
+
+}  // namespace qpk

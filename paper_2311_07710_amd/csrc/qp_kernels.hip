@@ -1,0 +1,959 @@
+// qp_kernels.hip -- gfx950 kernels of the single-instance rAPDHG hot path.
+//
+// Per iteration (Algorithm 1 of Lu & Yang, arXiv 2311.07710, in the
+// EQ/GE + bounds form L(x,y) = 1/2 x'Qx + c'x - y'(Ax - b)):
+//   dual phase   (k_dual):   y+ = proj_Y(y - d_k (A x~ - b)),  y-bar averaging
+//   primal phase (k_primal): x+ = proj_X(x - p_k (Q x_md + c - A'y+)),  x-bar
+//                            averaging, and the NEXT iteration's x~ and x_md
+// Every KKT check (Sec. 5 relative KKT error for z and z-bar):
+//   k_kkt_rows (A x, A x-bar), k_kkt_cols (Q x, A'y for both points), then the
+//   single-workgroup k_decide (Sec. 6 restart candidate, criteria (i)-(iii),
+//   primal weight update, step-size table for the next interval) and k_apply.
+//
+// Memory layout: A is CSR (m rows); Q and -A' are fused into ONE CSR matrix
+// P = [Q | -A'] (n rows, columns >= n address y), so the primal phase is a
+// single streaming pass gathering from (x_md, y).  Rows are grouped on the
+// host into blocks of <= NNZ_BLK nonzeros and <= BS rows; a workgroup streams
+// its nonzeros with coalesced non-temporal loads, gathers the vector entries
+// and stages the products in LDS, then each row is summed in CSR order
+// (several lanes per row only when a block holds few rows).  HBM-bound: no
+// MFMA anywhere on this path.
+#include <math.h>
+
+#include "qp_internal.h"
+
+namespace qpk {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of row blocks so neighbouring rows share an L2.
+__device__ __forceinline__ int xcd_block(int bid, int nb) {
+    const int X = 8;
+    const int q = nb / X, r = nb % X;
+    const int x = bid % X, local = bid / X;
+    return x * q + min(x, r) + local;
+}
+
+// max that keeps a NaN once seen (the reductions must report NaN)
+__device__ __forceinline__ double nmax(double a, double b) {
+    return (b > a || b != b) ? b : a;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = v + __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = nmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// group reduction over G lanes (G a power of two dividing 64)
+__device__ __forceinline__ double group_sum(double v, int G) {
+    for (int off = G >> 1; off >= 1; off >>= 1) v = v + __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int lanes_per_row(int nrows) {
+    int g = BS / (nrows > 0 ? nrows : 1);
+    g = g > 64 ? 64 : g;
+    return 1 << (31 - __clz(g));
+}
+
+// Deterministic block sum of the staged products prod[0..cnt).
+__device__ double block_sum_lds(const double *prod, int cnt, double *scratch) {
+    double s = 0.0;
+    for (int e = threadIdx.x; e < cnt; e += BS) s = s + prod[e];
+    s = wave_sum(s);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) scratch[wid] = s;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < BS / 64; ++w) t = t + scratch[w];
+    __syncthreads();
+    return t;  // valid in thread 0
+}
+
+// Chunk partial sums of a long row: thread 0 publishes its W partial sums;
+// the last chunk to arrive (atomic counter) adds all partials in chunk order.
+// Returns true in thread 0 of the last block, with the row totals in tot[].
+template <int W>
+__device__ bool chunk_finish(const Blocks &bk, int bi, int lr, const double *part, double *tot) {
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+        for (int v = 0; v < W; ++v) bk.lr_partial[(size_t)bi * 4 + v] = part[v];
+        __threadfence();
+        const int old = atomicAdd(&bk.lr_count[lr], 1);
+        is_last = (old == bk.lr_nchunk[lr] - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int f = bk.lr_first[lr], nc = bk.lr_nchunk[lr];
+        for (int v = 0; v < W; ++v) tot[v] = 0.0;
+        for (int ch = 0; ch < nc; ++ch)
+            for (int v = 0; v < W; ++v)
+                tot[v] = tot[v] + __hip_atomic_load(&bk.lr_partial[(size_t)(f + ch) * 4 + v],
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&bk.lr_count[lr], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return threadIdx.x == 0;
+}
+
+// ---------------------------------------------------------------------------
+// dual phase: one pass over A
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void dual_epilogue(int i, double v, double *__restrict__ y,
+                                              double *__restrict__ ybar,
+                                              const double *__restrict__ b,
+                                              const uint8_t *__restrict__ rt, double d, double w) {
+    double yn = y[i] - d * (v - b[i]);
+    if (rt[i] == 1 && yn < 0.0) yn = 0.0;  // projection onto y_i >= 0 for >= rows
+    ybar[i] = (1.0 - w) * ybar[i] + w * yn;
+    y[i] = yn;
+}
+
+__global__ __launch_bounds__(BS) void k_dual(Blocks bk, Csr A, const double *__restrict__ xt,
+                                             double *__restrict__ y, double *__restrict__ ybar,
+                                             const double *__restrict__ b,
+                                             const uint8_t *__restrict__ rt,
+                                             const Step *__restrict__ step,
+                                             const State *__restrict__ st) {
+    if (st->done) return;
+    __shared__ double prod[NNZ_BLK];
+    __shared__ double scratch[BS / 64];
+    const int bi = xcd_block(blockIdx.x, gridDim.x);
+    const Block B = bk.blk[bi];
+    const int t = threadIdx.x;
+    int cols[EPT];
+    double vals[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = B.e0 + i * BS + t;
+        if (e < B.e1) {
+            cols[i] = __builtin_nontemporal_load(&A.col[e]);
+            vals[i] = __builtin_nontemporal_load(&A.val[e]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = B.e0 + i * BS + t;
+        if (e < B.e1) prod[i * BS + t] = vals[i] * xt[cols[i]];
+    }
+    __syncthreads();
+    const double d = step->d, w = step->w;
+    const int lr = bk.lr[bi];
+    if (lr < 0) {
+        const int nrows = B.row1 - B.row0;
+        const int G = lanes_per_row(nrows);
+        const int rl = t / G, lane = t % G;
+        double s = 0.0;
+        if (rl < nrows) {
+            const int row = B.row0 + rl;
+            const int s1 = A.rowptr[row + 1] - B.e0;
+            for (int e = A.rowptr[row] - B.e0 + lane; e < s1; e += G) s = s + prod[e];
+        }
+        s = group_sum(s, G);
+        if (rl < nrows && lane == 0) dual_epilogue(B.row0 + rl, s, y, ybar, b, rt, d, w);
+    } else {
+        double part = block_sum_lds(prod, B.e1 - B.e0, scratch);
+        double tot;
+        if (chunk_finish<1>(bk, bi, lr, &part, &tot)) dual_epilogue(B.row0, tot, y, ybar, b, rt, d, w);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// primal phase: one pass over P = [Q | -A'] gathering (x_md, y+)
+// ---------------------------------------------------------------------------
+struct PrimalArgs {
+    const double *xmd_in;
+    const double *y;
+    double *x, *xbar, *xt, *xmd_out;
+    const double *c, *l, *u;
+};
+
+__device__ __forceinline__ void primal_epilogue(int j, double s, const PrimalArgs &a, double p,
+                                                double w, double th1, double w1) {
+    const double g = s + a.c[j];
+    const double xo = a.x[j];
+    double xn = xo - p * g;
+    const double lo = a.l[j], hi = a.u[j];
+    if (xn < lo) xn = lo;
+    if (xn > hi) xn = hi;
+    const double xb = (1.0 - w) * a.xbar[j] + w * xn;
+    a.x[j] = xn;
+    a.xbar[j] = xb;
+    a.xt[j] = xn + th1 * (xn - xo);          // x~ of the next iteration
+    a.xmd_out[j] = (1.0 - w1) * xb + w1 * xn;  // x_md of the next iteration
+}
+
+__global__ __launch_bounds__(BS) void k_primal(Blocks bk, Csr P, PrimalArgs a,
+                                               const Step *__restrict__ step,
+                                               const State *__restrict__ st, int32_t n) {
+    if (st->done) return;
+    __shared__ double prod[NNZ_BLK];
+    __shared__ double scratch[BS / 64];
+    const int bi = xcd_block(blockIdx.x, gridDim.x);
+    const Block B = bk.blk[bi];
+    const int t = threadIdx.x;
+    int cols[EPT];
+    double vals[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = B.e0 + i * BS + t;
+        if (e < B.e1) {
+            cols[i] = __builtin_nontemporal_load(&P.col[e]);
+            vals[i] = __builtin_nontemporal_load(&P.val[e]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = B.e0 + i * BS + t;
+        if (e < B.e1) {
+            const int cc = cols[i];
+            const double v = cc < n ? a.xmd_in[cc] : a.y[cc - n];
+            prod[i * BS + t] = vals[i] * v;
+        }
+    }
+    __syncthreads();
+    const double p = step->p, w = step->w, th1 = step->theta_next, w1 = step->w_next;
+    const int lr = bk.lr[bi];
+    if (lr < 0) {
+        const int nrows = B.row1 - B.row0;
+        const int G = lanes_per_row(nrows);
+        const int rl = t / G, lane = t % G;
+        double s = 0.0;
+        if (rl < nrows) {
+            const int row = B.row0 + rl;
+            const int s1 = P.rowptr[row + 1] - B.e0;
+            for (int e = P.rowptr[row] - B.e0 + lane; e < s1; e += G) s = s + prod[e];
+        }
+        s = group_sum(s, G);
+        if (rl < nrows && lane == 0) primal_epilogue(B.row0 + rl, s, a, p, w, th1, w1);
+    } else {
+        double part = block_sum_lds(prod, B.e1 - B.e0, scratch);
+        double tot;
+        if (chunk_finish<1>(bk, bi, lr, &part, &tot)) primal_epilogue(B.row0, tot, a, p, w, th1, w1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// KKT evaluation, rows of A: A x and A x-bar in one pass
+// ---------------------------------------------------------------------------
+struct KktRowArgs {
+    const double *x, *xbar, *y, *ybar, *yrs, *b;
+    const uint8_t *rt;
+    double *partials;  // [(nblk + nlr) * RA_NV]
+};
+
+__device__ __forceinline__ void kkt_row_contrib(int i, double s0, double s1, const KktRowArgs &a,
+                                                double *cv) {
+    const double bi = a.b[i];
+    const bool ge = a.rt[i] == 1;
+    double r0 = s0 - bi, r1 = s1 - bi;
+    if (ge) {
+        r0 = (r0 < 0.0) ? -r0 : 0.0;
+        r1 = (r1 < 0.0) ? -r1 : 0.0;
+    }
+    cv[RA_RES0] = fabs(r0);
+    cv[RA_RES1] = fabs(r1);
+    cv[RA_AX0] = fabs(s0);
+    cv[RA_AX1] = fabs(s1);
+    const double yi = a.y[i], ybi = a.ybar[i], yr = a.yrs[i];
+    cv[RA_BY0] = bi * yi;
+    cv[RA_BY1] = bi * ybi;
+    const double d0 = yi - yr, d1 = ybi - yr;
+    cv[RA_DY0] = d0 * d0;
+    cv[RA_DY1] = d1 * d1;
+}
+
+// block reduction of NV contributions (first NMAX are maxima, the rest sums),
+// written by thread 0 to out[0..NV)
+template <int NV, int NMAX>
+__device__ void block_reduce_write(double *cv, double *out) {
+    __shared__ double red[NV][BS / 64];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) cv[v] = v < NMAX ? wave_max(cv[v]) : wave_sum(cv[v]);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        for (int v = 0; v < NV; ++v) red[v][wid] = cv[v];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 0; v < NV; ++v) {
+            double acc = red[v][0];
+            for (int w = 1; w < BS / 64; ++w) acc = v < NMAX ? nmax(acc, red[v][w]) : acc + red[v][w];
+            out[v] = acc;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_kkt_rows(Blocks bk, Csr A, KktRowArgs a,
+                                                 const State *__restrict__ st) {
+    if (st->done) return;
+    __shared__ double prod0[NNZ_BLK];
+    __shared__ double prod1[NNZ_BLK];
+    __shared__ double scratch[BS / 64];
+    const int bi = xcd_block(blockIdx.x, gridDim.x);
+    const Block B = bk.blk[bi];
+    const int t = threadIdx.x;
+    for (int i = 0; i < EPT; ++i) {
+        const int e = B.e0 + i * BS + t;
+        if (e < B.e1) {
+            const int cc = A.col[e];
+            const double v = A.val[e];
+            prod0[i * BS + t] = v * a.x[cc];
+            prod1[i * BS + t] = v * a.xbar[cc];
+        }
+    }
+    __syncthreads();
+    double cv[RA_NV];
+    for (int v = 0; v < RA_NV; ++v) cv[v] = 0.0;
+    const int lr = bk.lr[bi];
+    if (lr < 0) {
+        const int nrows = B.row1 - B.row0;
+        const int G = lanes_per_row(nrows);
+        const int rl = t / G, lane = t % G;
+        double s0 = 0.0, s1 = 0.0;
+        if (rl < nrows) {
+            const int row = B.row0 + rl;
+            const int e1 = A.rowptr[row + 1] - B.e0;
+            for (int e = A.rowptr[row] - B.e0 + lane; e < e1; e += G) {
+                s0 = s0 + prod0[e];
+                s1 = s1 + prod1[e];
+            }
+        }
+        s0 = group_sum(s0, G);
+        s1 = group_sum(s1, G);
+        if (rl < nrows && lane == 0) kkt_row_contrib(B.row0 + rl, s0, s1, a, cv);
+        block_reduce_write<RA_NV, 4>(cv, a.partials + (size_t)bi * RA_NV);
+    } else {
+        double part[2];
+        part[0] = block_sum_lds(prod0, B.e1 - B.e0, scratch);
+        part[1] = block_sum_lds(prod1, B.e1 - B.e0, scratch);
+        if (t == 0)
+            for (int v = 0; v < RA_NV; ++v) a.partials[(size_t)bi * RA_NV + v] = 0.0;
+        double tot[2];
+        if (chunk_finish<2>(bk, bi, lr, part, tot)) {
+            kkt_row_contrib(B.row0, tot[0], tot[1], a, cv);
+            for (int v = 0; v < RA_NV; ++v)
+                a.partials[(size_t)(bk.nblk + lr) * RA_NV + v] = cv[v];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// KKT evaluation, rows of P = [Q | -A']: Q x and A'y for z and z-bar
+// ---------------------------------------------------------------------------
+struct KktColArgs {
+    const double *x, *xbar, *y, *ybar, *xrs, *c, *l, *u;
+    double *partials;  // [(nblk + nlr) * RP_NV]
+};
+
+__device__ __forceinline__ void kkt_col_contrib(int j, const double *qx, const double *naty,
+                                                const KktColArgs &a, double *cv) {
+    const double cj = a.c[j], lj = a.l[j], uj = a.u[j];
+    const bool lo_fin = isfinite(lj), hi_fin = isfinite(uj);
+    for (int p = 0; p < 2; ++p) {
+        const double xp = p == 0 ? a.x[j] : a.xbar[j];
+        const double aty = -naty[p];
+        const double lam = qx[p] + cj - aty;  // reduced cost Qx + c - A'y
+        double lam_hat;
+        if (lo_fin && hi_fin) lam_hat = lam;
+        else if (lo_fin) lam_hat = lam > 0.0 ? lam : 0.0;
+        else if (hi_fin) lam_hat = lam < 0.0 ? lam : 0.0;
+        else lam_hat = 0.0;
+        cv[RP_DRES0 + p] = fabs(lam - lam_hat);
+        cv[RP_QX0 + p] = fabs(qx[p]);
+        cv[RP_ATY0 + p] = fabs(aty);
+        cv[RP_XQX0 + p] = xp * qx[p];
+        cv[RP_CX0 + p] = cj * xp;
+        double bnd = 0.0;
+        if (lo_fin && lam_hat > 0.0) bnd = lj * lam_hat;
+        if (hi_fin && lam_hat < 0.0) bnd = uj * lam_hat;
+        cv[RP_BND0 + p] = bnd;
+        const double dx = xp - a.xrs[j];
+        cv[RP_DX0 + p] = dx * dx;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_kkt_cols(Blocks bk, Csr P, KktColArgs a,
+                                                 const State *__restrict__ st, int32_t n) {
+    if (st->done) return;
+    __shared__ double prod0[NNZ_BLK];
+    __shared__ double prod1[NNZ_BLK];
+    __shared__ uint8_t isA[NNZ_BLK];
+    __shared__ double scratch[BS / 64];
+    const int bi = xcd_block(blockIdx.x, gridDim.x);
+    const Block B = bk.blk[bi];
+    const int t = threadIdx.x;
+    for (int i = 0; i < EPT; ++i) {
+        const int e = B.e0 + i * BS + t;
+        if (e < B.e1) {
+            const int cc = P.col[e];
+            const double v = P.val[e];
+            const bool ya = cc >= n;
+            prod0[i * BS + t] = v * (ya ? a.y[cc - n] : a.x[cc]);
+            prod1[i * BS + t] = v * (ya ? a.ybar[cc - n] : a.xbar[cc]);
+            isA[i * BS + t] = ya;
+        }
+    }
+    __syncthreads();
+    double cv[RP_NV];
+    for (int v = 0; v < RP_NV; ++v) cv[v] = 0.0;
+    const int lr = bk.lr[bi];
+    if (lr < 0) {
+        const int nrows = B.row1 - B.row0;
+        const int G = lanes_per_row(nrows);
+        const int rl = t / G, lane = t % G;
+        double q[2] = {0.0, 0.0}, na[2] = {0.0, 0.0};
+        if (rl < nrows) {
+            const int row = B.row0 + rl;
+            const int e1 = P.rowptr[row + 1] - B.e0;
+            for (int e = P.rowptr[row] - B.e0 + lane; e < e1; e += G) {
+                if (isA[e]) {
+                    na[0] = na[0] + prod0[e];
+                    na[1] = na[1] + prod1[e];
+                } else {
+                    q[0] = q[0] + prod0[e];
+                    q[1] = q[1] + prod1[e];
+                }
+            }
+        }
+        for (int p = 0; p < 2; ++p) {
+            q[p] = group_sum(q[p], G);
+            na[p] = group_sum(na[p], G);
+        }
+        if (rl < nrows && lane == 0) kkt_col_contrib(B.row0 + rl, q, na, a, cv);
+        block_reduce_write<RP_NV, 6>(cv, a.partials + (size_t)bi * RP_NV);
+    } else {
+        // split the staged products of this chunk into the Q part and the A' part
+        double part[4];
+        for (int p = 0; p < 4; ++p) {
+            double s = 0.0;
+            const double *src = (p & 1) ? prod1 : prod0;
+            const bool wantA = p >= 2;
+            for (int e = t; e < B.e1 - B.e0; e += BS)
+                if ((bool)isA[e] == wantA) s = s + src[e];
+            s = wave_sum(s);
+            if ((t & 63) == 0) scratch[t >> 6] = s;
+            __syncthreads();
+            if (t == 0) {
+                double acc = 0.0;
+                for (int w = 0; w < BS / 64; ++w) acc = acc + scratch[w];
+                part[p] = acc;
+            }
+            __syncthreads();
+        }
+        if (t == 0)
+            for (int v = 0; v < RP_NV; ++v) a.partials[(size_t)bi * RP_NV + v] = 0.0;
+        double tot[4];
+        if (chunk_finish<4>(bk, bi, lr, part, tot)) {
+            double q[2] = {tot[0], tot[1]}, na[2] = {tot[2], tot[3]};
+            kkt_col_contrib(B.row0, q, na, a, cv);
+            for (int v = 0; v < RP_NV; ++v)
+                a.partials[(size_t)(bk.nblk + lr) * RP_NV + v] = cv[v];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// decision kernel (one workgroup): relKKT, candidate, restart, primal weight,
+// step table for the next interval
+// ---------------------------------------------------------------------------
+// Sec. 6 step-size cap at inner index k: 0.99 (k+2) / (||Q||/w + sqrt(||A||^2 (k+2)^2 + ||Q||^2/w^2))
+__device__ double pdqp_cap(const DevSettings &s, double omega, int64_t k) {
+    const double kk = (double)(k + 2);
+    const double qw = s.norm_Q / omega;
+    return s.step_safety * kk / (qw + sqrt(s.norm_A * s.norm_A * kk * kk + qw * qw));
+}
+
+__device__ void step_at(const DevSettings &s, double omega, int64_t k, double *s_last, double *p,
+                        double *d) {
+    if (s.restart_mode == MODE_FIXED_K) {  // Theorem 1 / eq. (param-choice)
+        const double Kf = (double)s.fixed_K;
+        *p = (double)(k + 1) / (2.0 * (s.norm_Q + Kf * s.norm_A));
+        *d = s.norm_A > 0.0 ? (double)(k + 1) / (2.0 * Kf * s.norm_A) : 0.0;
+        *s_last = 0.0;
+        return;
+    }
+    const double cap = pdqp_cap(s, omega, k);
+    double sk;
+    if (k == 0) {
+        sk = cap;
+    } else {
+        const double grown = (1.0 + 1.0 / (double)k) * (*s_last);
+        sk = grown < cap ? grown : cap;
+    }
+    *s_last = sk;
+    *p = sk / omega;
+    *d = sk * omega;
+}
+
+__device__ void rel_kkt_point(const double *ra, const double *rp, int p, const DevSettings &s,
+                              double *out) {
+    const double res_p = ra[RA_RES0 + p], ax = ra[RA_AX0 + p], by = ra[RA_BY0 + p];
+    const double dres = rp[RP_DRES0 + p], qx = rp[RP_QX0 + p], aty = rp[RP_ATY0 + p];
+    const double xqx = rp[RP_XQX0 + p], cx = rp[RP_CX0 + p], bnd = rp[RP_BND0 + p];
+    const double P = 0.5 * xqx + cx;
+    const double D = -0.5 * xqx + by + bnd;
+    const double r_p = res_p / (1.0 + fmax(ax, s.b_inf));
+    const double r_d = dres / (1.0 + fmax(fmax(qx, aty), s.c_inf));
+    const double r_g = fabs(P - D) / (1.0 + fmax(fabs(P), fabs(D)));
+    double r = r_p;
+    if (r_d > r) r = r_d;
+    if (r_g > r) r = r_g;
+    if (isnan(r_p) || isnan(r_d) || isnan(r_g)) r = NAN;
+    out[0] = r_p;
+    out[1] = r_d;
+    out[2] = r_g;
+    out[3] = r;
+    out[4] = P;
+    out[5] = D;
+}
+
+__global__ __launch_bounds__(BS) void k_decide(int mode, const double *__restrict__ partA,
+                                               int32_t nslotA, const double *__restrict__ partP,
+                                               int32_t nslotP, State *st, Step *table,
+                                               DevSettings s, int32_t len) {
+    if (st->done) return;
+    __shared__ double red[RA_NV + RP_NV][BS];
+    const int t = threadIdx.x;
+    // fixed-order reduction of the block partials
+    for (int v = 0; v < RA_NV; ++v) {
+        const bool mx = v < 4;
+        double acc = 0.0;
+        for (int i = t; i < nslotA; i += BS) {
+            const double z = partA[(size_t)i * RA_NV + v];
+            acc = mx ? nmax(acc, z) : acc + z;
+        }
+        red[v][t] = acc;
+    }
+    for (int v = 0; v < RP_NV; ++v) {
+        const bool mx = v < 6;
+        double acc = 0.0;
+        for (int i = t; i < nslotP; i += BS) {
+            const double z = partP[(size_t)i * RP_NV + v];
+            acc = mx ? nmax(acc, z) : acc + z;
+        }
+        red[RA_NV + v][t] = acc;
+    }
+    __syncthreads();
+    for (int h = BS / 2; h >= 1; h >>= 1) {
+        if (t < h) {
+            for (int v = 0; v < RA_NV + RP_NV; ++v) {
+                const bool mx = v < RA_NV ? v < 4 : (v - RA_NV) < 6;
+                red[v][t] = mx ? nmax(red[v][t], red[v][t + h]) : red[v][t] + red[v][t + h];
+            }
+        }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    double ra[RA_NV], rp[RP_NV];
+    for (int v = 0; v < RA_NV; ++v) ra[v] = red[v][0];
+    for (int v = 0; v < RP_NV; ++v) rp[v] = red[RA_NV + v][0];
+    double k0[6], k1[6];
+    rel_kkt_point(ra, rp, 0, s, k0);
+    rel_kkt_point(ra, rp, 1, s, k1);
+
+    State S = *st;
+    int restart = 0;
+    if (mode == DECIDE_FALLBACK) {
+        // point 0 = warm start, point 1 = cold start
+        S.used_warm = k0[3] < k1[3] ? 1 : 0;
+        S.kkt_evals += 2;
+        *st = S;
+        return;
+    }
+    if (mode == DECIDE_INIT) {
+        S.kkt_evals += 1;
+        S.r0 = k0[3];
+        S.prev_cand = INFINITY;
+        S.total = 0;
+        S.k = 0;
+        S.cand = 0;
+        S.r_cur = S.r_avg = k0[3];
+        for (int i = 0; i < 6; ++i) S.kkt[0][i] = S.kkt[1][i] = k0[i];
+        if (isnan(k0[3])) {
+            S.status = ST_NUMERICAL;
+            S.done = 1;
+        } else if (k0[3] <= s.eps) {
+            S.status = ST_OPTIMAL;
+            S.done = 1;
+        } else if (s.max_iter <= 0) {
+            S.status = ST_ITER_LIMIT;
+            S.done = 1;
+        }
+    } else {  // DECIDE_CHECK after `len` iterations
+        S.total += len;
+        S.k += len;
+        S.kkt_evals += 2;
+        S.checks += 1;
+        const double r = k0[3], rb = k1[3];
+        const bool fixed = s.restart_mode == MODE_FIXED_K;
+        int cand_avg = fixed ? 1 : !(r < rb);
+        double rc = cand_avg ? rb : r;
+        if (isnan(r) || isnan(rb)) {
+            S.status = ST_NUMERICAL;
+            S.done = 1;
+        } else if (rc <= s.eps) {
+            S.status = ST_OPTIMAL;
+            S.done = 1;
+        } else if (S.total >= s.max_iter) {
+            S.status = ST_ITER_LIMIT;
+            S.done = 1;
+        } else if (s.restart_mode == MODE_ADAPTIVE) {
+            restart = (rc <= s.beta_sufficient * S.r0) ||
+                      (rc <= s.beta_necessary * S.r0 && rc > S.prev_cand) ||
+                      ((double)S.k >= s.beta_artificial * (double)S.total);
+        } else if (s.restart_mode == MODE_HALVING) {
+            restart = rb <= 0.5 * S.r0;
+            if (restart) {
+                cand_avg = 1;
+                rc = rb;
+            }
+        } else if (fixed) {
+            restart = 1;
+        }
+        if (restart) {
+            if (!fixed) {  // Sec. 6 primal weight update
+                const double dx = sqrt(rp[RP_DX0 + cand_avg]);
+                const double dy = sqrt(ra[RA_DY0 + cand_avg]);
+                if (dx > s.eps_zero && dy > s.eps_zero)
+                    S.omega = exp(s.pw_smoothing * log(dy / dx) +
+                                  (1.0 - s.pw_smoothing) * log(S.omega));
+            }
+            S.k = 0;
+            S.r0 = rc;
+            S.prev_cand = INFINITY;
+            S.restarts += 1;
+        } else if (!S.done) {
+            S.prev_cand = rc;
+        }
+        S.cand = cand_avg;
+        S.r_cur = r;
+        S.r_avg = rb;
+        for (int i = 0; i < 6; ++i) {
+            S.kkt[0][i] = k0[i];
+            S.kkt[1][i] = k1[i];
+        }
+    }
+    S.restart_flag = restart;
+    if (!S.done) {
+        double sl = S.s_last;
+        for (int j = 0; j < s.interval; ++j) {
+            const int64_t kj = S.k + j;
+            double p, d;
+            step_at(s, S.omega, kj, &sl, &p, &d);
+            Step e;
+            e.p = p;
+            e.d = d;
+            e.w = 2.0 / (double)(kj + 2);
+            e.theta_next = (double)(kj + 1) / (double)(kj + 2);
+            e.w_next = 2.0 / (double)(kj + 3);
+            e.pad[0] = e.pad[1] = e.pad[2] = 0.0;
+            table[j] = e;
+        }
+        S.s_last = sl;
+    }
+    *st = S;
+}
+
+// ---------------------------------------------------------------------------
+// restart application, initialisation, state reset
+// ---------------------------------------------------------------------------
+__global__ void k_apply(Vecs v, double *xmd_out, const State *__restrict__ st, int64_t n,
+                        int64_t m) {
+    if (!st->restart_flag) return;
+    const int avg = st->cand;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const double xc = avg ? v.xbar[j] : v.x[j];
+        v.x[j] = xc;
+        v.xbar[j] = xc;
+        v.xt[j] = xc;
+        xmd_out[j] = xc;
+        v.xrs[j] = xc;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const double yc = avg ? v.ybar[i] : v.y[i];
+        v.y[i] = yc;
+        v.ybar[i] = yc;
+        v.yrs[i] = yc;
+    }
+}
+
+__device__ __forceinline__ double proj_box(double v, double lo, double hi) {
+    if (v < lo) v = lo;
+    if (v > hi) v = hi;
+    return v;
+}
+
+__global__ void k_init(Vecs v, const double *x0, const double *y0, int64_t n, int64_t m,
+                       int pair) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const double lo = v.l[j], hi = v.u[j];
+        const double xc = proj_box(0.0, lo, hi);
+        const double xw = x0 ? proj_box(x0[j], lo, hi) : xc;
+        v.x[j] = xw;
+        v.xbar[j] = pair ? xc : xw;
+        v.xt[j] = xw;
+        v.xmd[0][j] = xw;
+        v.xrs[j] = xw;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        double yw = y0 ? y0[i] : 0.0;
+        if (v.rt[i] == 1 && yw < 0.0) yw = 0.0;
+        v.y[i] = yw;
+        v.ybar[i] = pair ? 0.0 : yw;
+        v.yrs[i] = yw;
+    }
+}
+
+__global__ void k_fallback_apply(Vecs v, const State *__restrict__ st, int64_t n, int64_t m) {
+    const int take = st->used_warm;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        const double xv = take ? v.x[j] : v.xbar[j];
+        v.x[j] = xv;
+        v.xbar[j] = xv;
+        v.xt[j] = xv;
+        v.xmd[0][j] = xv;
+        v.xrs[j] = xv;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const double yv = take ? v.y[i] : v.ybar[i];
+        v.y[i] = yv;
+        v.ybar[i] = yv;
+        v.yrs[i] = yv;
+    }
+}
+
+__global__ void k_state_reset(State *st, double omega, int64_t max_iter) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    State S;
+    S.omega = omega;
+    S.r0 = 0.0;
+    S.prev_cand = INFINITY;
+    S.s_last = 0.0;
+    S.r_cur = S.r_avg = 0.0;
+    for (int p = 0; p < 2; ++p)
+        for (int i = 0; i < 6; ++i) S.kkt[p][i] = 0.0;
+    S.total = 0;
+    S.k = 0;
+    S.restarts = 0;
+    S.kkt_evals = 0;
+    S.done = 0;
+    S.status = -1;
+    S.cand = 0;
+    S.restart_flag = 0;
+    S.used_warm = 0;
+    S.checks = 0;
+    S.pad0 = S.pad1 = 0;
+    (void)max_iter;
+    *st = S;
+}
+
+// ---------------------------------------------------------------------------
+// power iteration helpers
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void k_spmv_plain(Blocks bk, Csr M, const double *x,
+                                                   const double *x2, int32_t split, double *y,
+                                                   double sign2) {
+    __shared__ double prod[NNZ_BLK];
+    __shared__ double scratch[BS / 64];
+    const int bi = xcd_block(blockIdx.x, gridDim.x);
+    const Block B = bk.blk[bi];
+    const int t = threadIdx.x;
+    for (int i = 0; i < EPT; ++i) {
+        const int e = B.e0 + i * BS + t;
+        if (e < B.e1) {
+            const int cc = M.col[e];
+            const double v = M.val[e];
+            double pr = 0.0;
+            if (cc < split) {
+                if (x) pr = v * x[cc];
+            } else if (x2) {
+                pr = sign2 * (v * x2[cc - split]);
+            }
+            prod[i * BS + t] = pr;
+        }
+    }
+    __syncthreads();
+    const int lr = bk.lr[bi];
+    if (lr < 0) {
+        const int nrows = B.row1 - B.row0;
+        const int G = lanes_per_row(nrows);
+        const int rl = t / G, lane = t % G;
+        double s = 0.0;
+        if (rl < nrows) {
+            const int row = B.row0 + rl;
+            const int e1 = M.rowptr[row + 1] - B.e0;
+            for (int e = M.rowptr[row] - B.e0 + lane; e < e1; e += G) s = s + prod[e];
+        }
+        s = group_sum(s, G);
+        if (rl < nrows && lane == 0) y[B.row0 + rl] = s;
+    } else {
+        double part = block_sum_lds(prod, B.e1 - B.e0, scratch);
+        double tot;
+        if (chunk_finish<1>(bk, bi, lr, &part, &tot)) y[B.row0] = tot;
+    }
+}
+
+int dot_nparts(int64_t n) {
+    int64_t p = (n + 8191) / 8192;
+    if (p < 1) p = 1;
+    if (p > 1024) p = 1024;
+    return (int)p;
+}
+
+__global__ __launch_bounds__(BS) void k_dot_partials(const double *a, const double *b, int64_t n,
+                                                     double *partials, int32_t nparts) {
+    __shared__ double scratch[BS / 64];
+    const int64_t chunk = (n + nparts - 1) / nparts;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += BS) s = s + a[i] * b[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int w = 0; w < BS / 64; ++w) acc = acc + scratch[w];
+        partials[blockIdx.x] = acc;
+    }
+}
+
+__global__ void k_div(double *dst, const double *src, int64_t n, double den) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = src[i] / den;
+}
+
+__global__ void k_fill(double *dst, int64_t n, double value) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (int)g;
+}
+
+void launch_dual(hipStream_t s, const Blocks &bk, const Csr &A, const Vecs &v, const Step *step,
+                 const State *st) {
+    if (bk.nblk == 0) return;
+    hipLaunchKernelGGL(k_dual, dim3(bk.nblk), dim3(BS), 0, s, bk, A, v.xt, v.y, v.ybar, v.b, v.rt,
+                       step, st);
+}
+
+void launch_primal(hipStream_t s, const Blocks &bk, const Csr &P, const Vecs &v, int md_in,
+                   const Step *step, const State *st, int64_t n) {
+    if (bk.nblk == 0) return;
+    PrimalArgs a;
+    a.xmd_in = v.xmd[md_in];
+    a.y = v.y;
+    a.x = v.x;
+    a.xbar = v.xbar;
+    a.xt = v.xt;
+    a.xmd_out = v.xmd[md_in ^ 1];
+    a.c = v.c;
+    a.l = v.l;
+    a.u = v.u;
+    hipLaunchKernelGGL(k_primal, dim3(bk.nblk), dim3(BS), 0, s, bk, P, a, step, st, (int32_t)n);
+}
+
+void launch_kkt_rows(hipStream_t s, const Blocks &bk, const Csr &A, const Vecs &v,
+                     double *partials, const State *st) {
+    if (bk.nblk == 0) return;
+    KktRowArgs a;
+    a.x = v.x;
+    a.xbar = v.xbar;
+    a.y = v.y;
+    a.ybar = v.ybar;
+    a.yrs = v.yrs;
+    a.b = v.b;
+    a.rt = v.rt;
+    a.partials = partials;
+    hipLaunchKernelGGL(k_kkt_rows, dim3(bk.nblk), dim3(BS), 0, s, bk, A, a, st);
+}
+
+void launch_kkt_cols(hipStream_t s, const Blocks &bk, const Csr &P, const Vecs &v,
+                     double *partials, const State *st, int64_t n) {
+    if (bk.nblk == 0) return;
+    KktColArgs a;
+    a.x = v.x;
+    a.xbar = v.xbar;
+    a.y = v.y;
+    a.ybar = v.ybar;
+    a.xrs = v.xrs;
+    a.c = v.c;
+    a.l = v.l;
+    a.u = v.u;
+    a.partials = partials;
+    hipLaunchKernelGGL(k_kkt_cols, dim3(bk.nblk), dim3(BS), 0, s, bk, P, a, st, (int32_t)n);
+}
+
+void launch_decide(hipStream_t s, int mode, const double *partA, int32_t nslotA,
+                   const double *partP, int32_t nslotP, State *st, Step *table,
+                   const DevSettings &ds, int32_t len) {
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(BS), 0, s, mode, partA, nslotA, partP, nslotP, st,
+                       table, ds, len);
+}
+
+void launch_apply(hipStream_t s, const Vecs &v, int md_out, const State *st, int64_t n,
+                  int64_t m) {
+    hipLaunchKernelGGL(k_apply, dim3(grid_for(n > m ? n : m)), dim3(256), 0, s, v, v.xmd[md_out],
+                       st, n, m);
+}
+
+void launch_init(hipStream_t s, const Vecs &v, const double *x0, const double *y0, int64_t n,
+                 int64_t m, int pair_with_cold) {
+    hipLaunchKernelGGL(k_init, dim3(grid_for(n > m ? n : m)), dim3(256), 0, s, v, x0, y0, n, m,
+                       pair_with_cold);
+}
+
+void launch_fallback_apply(hipStream_t s, const Vecs &v, const State *st, int64_t n, int64_t m) {
+    hipLaunchKernelGGL(k_fallback_apply, dim3(grid_for(n > m ? n : m)), dim3(256), 0, s, v, st, n,
+                       m);
+}
+
+void launch_state_reset(hipStream_t s, State *st, double omega, int64_t max_iter) {
+    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, st, omega, max_iter);
+}
+
+void launch_spmv_plain(hipStream_t s, const Blocks &bk, const Csr &M, const double *x,
+                       const double *x2, int64_t split, double *y, double sign2) {
+    if (bk.nblk == 0) return;
+    hipLaunchKernelGGL(k_spmv_plain, dim3(bk.nblk), dim3(BS), 0, s, bk, M, x, x2, (int32_t)split,
+                       y, sign2);
+}
+
+void launch_dot_partials(hipStream_t s, const double *a, const double *b, int64_t n,
+                         double *partials, int32_t nparts) {
+    hipLaunchKernelGGL(k_dot_partials, dim3(nparts), dim3(BS), 0, s, a, b, n, partials, nparts);
+}
+
+void launch_div(hipStream_t s, double *dst, const double *src, int64_t n, double den) {
+    hipLaunchKernelGGL(k_div, dim3(grid_for(n)), dim3(256), 0, s, dst, src, n, den);
+}
+
+void launch_fill(hipStream_t s, double *dst, int64_t n, double value) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, dst, n, value);
+}
+
+}  // namespace qpk

@@ -1,0 +1,127 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/qp.h, its struct layouts match the binding, defaults carry
+the paper's constants, and malformed host input is rejected before any device
+work (no compute call is made here)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2311_07710_amd as qpa
+from paper_2311_07710_amd import _binding as B
+from paper_2311_07710_amd.solver import Settings, _desc, _Keep
+import qpgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qp.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qp_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = qpa.load()
+    names = _declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.SIGNATURES)
+    assert lib.qp_version() == 1
+
+
+def test_struct_layouts_match_header(tmp_path):
+    structs = ["qp_csr", "qp_problem_desc", "qp_settings", "qp_warm_start", "qp_result",
+               "qp_check_info", "qp_profile"]
+    prog = tmp_path / "sz.c"
+    body = "\n".join(f'printf("{s} %zu\\n", sizeof({s}));' for s in structs)
+    offs = "\n".join(f'printf("off {s}.{f} %zu\\n", offsetof({s}, {f}));'
+                     for s in ("qp_settings", "qp_result")
+                     for f, _ in getattr(B, s)._fields_)
+    prog.write_text(f'#include <stdio.h>\n#include <stddef.h>\n#include "{HEADER}"\n'
+                    f"int main(void){{{body}\n{offs}\nreturn 0;}}\n")
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-o", str(exe), str(prog)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        parts = line.split()
+        if len(parts) == 2:
+            got[parts[0]] = int(parts[1])
+        elif len(parts) == 3:
+            got[parts[1]] = int(parts[2])
+    for s in structs:
+        assert got[s] == C.sizeof(getattr(B, s)), s
+    for s in ("qp_settings", "qp_result"):
+        cls = getattr(B, s)
+        for f, _ in cls._fields_:
+            assert got[f"{s}.{f}"] == getattr(cls, f).offset, (s, f)
+
+
+def test_default_settings_carry_paper_constants():
+    lib = qpa.load()
+    s = B.qp_settings()
+    lib.qp_default_settings(C.byref(s))
+    assert s.eps == 1e-6 and s.max_iter == 200000 and s.time_limit_s == 3600.0
+    assert (s.beta_sufficient, s.beta_necessary, s.beta_artificial) == (0.2, 0.8, 0.36)
+    assert s.pw_smoothing == 0.2 and s.step_safety == 0.99
+    assert s.restart_mode == B.QP_RESTART_ADAPTIVE and s.check_every == 64
+    py = Settings()
+    for name, _ in B.qp_settings._fields_:
+        assert getattr(py, name) == getattr(s, name), name
+
+
+def _create_rc(qp, **settings):
+    lib = qpa.load()
+    keep = _Keep(False)
+    d = _desc(qp, keep, batch=False)
+    h = C.c_void_p()
+    rc = lib.qp_create(C.byref(d), C.byref(Settings(**settings).c_struct()), C.byref(h))
+    if rc == 0:
+        lib.qp_free(h)
+    return rc, lib.qp_last_error().decode()
+
+
+def _tiny():
+    return qpgen.tiny_random_qp(1)
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda q: q.a_rowptr.__setitem__(3, q.a_rowptr[4] + 1), "A.row_ptr decreases"),
+    (lambda q: q.a_col.__setitem__(7, 100), "A.col_idx[7] = 100 out of range"),
+    (lambda q: q.q_col.__setitem__(0, -1), "Q.col_idx[0] = -1"),
+    (lambda q: q.row_type.__setitem__(2, 7), "row_type[2] = 7"),
+    (lambda q: (q.l.__setitem__(5, 3.0), q.u.__setitem__(5, 2.0)), "invalid bounds at variable 5"),
+    (lambda q: q.l.__setitem__(4, np.inf), "invalid bounds at variable 4"),
+])
+def test_malformed_input_rejected_on_host(mutate, needle):
+    qp = _tiny()
+    qp.a_rowptr = qp.a_rowptr.copy(); qp.a_col = qp.a_col.copy(); qp.q_col = qp.q_col.copy()
+    qp.row_type = qp.row_type.copy(); qp.l = qp.l.copy(); qp.u = qp.u.copy()
+    mutate(qp)
+    rc, msg = _create_rc(qp)
+    assert rc == B.QP_ERR_INVALID_ARGUMENT
+    assert needle in msg
+
+
+@pytest.mark.parametrize("kw,needle", [({"check_every": 0}, "check_every"),
+                                       ({"restart_mode": 9}, "restart_mode"),
+                                       ({"restart_mode": 1, "fixed_K": 0}, "fixed_K"),
+                                       ({"eps": -1.0}, "eps")])
+def test_bad_settings_rejected(kw, needle):
+    rc, msg = _create_rc(_tiny(), **kw)
+    assert rc == B.QP_ERR_INVALID_ARGUMENT and needle in msg
+
+
+def test_null_arguments():
+    lib = qpa.load()
+    assert lib.qp_create(None, None, None) == B.QP_ERR_INVALID_ARGUMENT
+    lib.qp_free(None)
+    r = B.qp_result()
+    assert lib.qp_solve(None, None, C.byref(r), None, None) == B.QP_ERR_INVALID_ARGUMENT
+    assert "null" in lib.qp_last_error().decode()

@@ -1,0 +1,307 @@
+"""GPU path vs CPU oracle, element by element, through the C-ABI.
+
+Both sides get the same seeded instance and the same operator norms (the
+oracle's power-iteration values are passed to the library as overrides, so
+step sizes agree).  Tolerances (FP64):
+  * relKKT of the returned point: |gpu - oracle| <= 1e-8 (the metric is
+    already relative);
+  * primal objective: |gpu - oracle| <= 1e-8 (1 + |oracle|);
+  * iterates (diagnostic): ||z_gpu - z_or||_inf <= 1e-8 (1 + ||z_or||_inf);
+  * iteration counts, restart counts and the evaluation log (iteration,
+    candidate, restart flag) identical.
+The GPU's reported relKKT is also re-evaluated by the oracle's own KKT routine
+at the GPU's returned point (1e-7 relative; the gap term's cancellation makes
+reduction-order effects ~1e-9): this pins the KKT kernels independently of the
+trajectory.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import qpgen
+from tests import qp_refs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qpa():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    import paper_2311_07710_amd as m
+    m.load()
+    return m
+
+
+def _norms(orc, qp):
+    nA, _ = orc.norm_A(qp, 1000, 1e-7)
+    nQ, _ = orc.norm_Q(qp, 1000, 1e-7)
+    return nA, nQ
+
+
+def _pair(orc, qpa, qp, *, eps=1e-6, max_iter=200000, check_every=64, mode=0, fixed_K=100,
+          x0=None, y0=None, omega0=0.0, warm_fallback=1, use_graph=1, norms=None, log=True):
+    nA, nQ = norms if norms is not None else _norms(orc, qp)
+    os_ = orc.OracleSettings(eps=eps, max_iter=max_iter, check_every=check_every,
+                             restart_mode=mode, fixed_K=fixed_K, norm_A=nA, norm_Q=nQ,
+                             warm_fallback=warm_fallback)
+    xo, yo, ro, lo = orc.solve(qp, os_, x0=x0, y0=y0, omega0=omega0, log_cap=100000)
+    gs = qpa.Settings(eps=eps, max_iter=max_iter, check_every=check_every, restart_mode=mode,
+                      fixed_K=fixed_K, norm_A=nA, norm_Q=nQ, warm_fallback=warm_fallback,
+                      use_graph=use_graph, log_checks=1 if log else 0)
+    with qpa.Solver(qp, gs) as s:
+        xg, yg, rg = s.solve(x0=x0, y0=y0, omega0=omega0)
+        lg = s.check_log()
+    return (xo, yo, ro, lo), (xg, yg, rg, lg)
+
+
+def _assert_parity(orc, qp, o, g, *, z_tol=1e-8, check_log=True):
+    xo, yo, ro, lo = o
+    xg, yg, rg, lg = g
+    print(f"  oracle: status={ro['status']} it={ro['iterations']} restarts={ro['restarts']} "
+          f"relKKT={ro['rel_kkt']:.3e} obj={ro['primal_obj']:.12g}", flush=True)
+    print(f"  gpu:    status={rg['status']} it={rg['iterations']} restarts={rg['restarts']} "
+          f"relKKT={rg['rel_kkt']:.3e} obj={rg['primal_obj']:.12g}", flush=True)
+    assert rg["status"] == ro["status"]
+    assert rg["iterations"] == ro["iterations"]
+    assert rg["restarts"] == ro["restarts"]
+    assert rg["kkt_evals"] == ro["kkt_evals"]
+    assert rg["used_warm_start"] == ro["used_warm_start"]
+    assert abs(rg["rel_kkt"] - ro["rel_kkt"]) <= 1e-8
+    assert abs(rg["primal_obj"] - ro["primal_obj"]) <= 1e-8 * (1 + abs(ro["primal_obj"]))
+    assert abs(rg["dual_obj"] - ro["dual_obj"]) <= 1e-8 * (1 + abs(ro["dual_obj"]))
+    # omega is driven by restart distances, which near machine-precision convergence are
+    # themselves rounding noise: agreement to 1e-6 relative
+    assert rg["omega"] == pytest.approx(ro["omega"], rel=1e-6)
+    zo = np.concatenate([xo, yo])
+    zg = np.concatenate([xg, yg])
+    assert np.max(np.abs(zg - zo)) <= z_tol * (1 + np.max(np.abs(zo)))
+    # the GPU's KKT kernels, re-checked at the GPU's own point
+    k = orc.rel_kkt(qp, xg, yg)
+    # (block-ordered reductions vs sequential sums; the gap term cancels P - D, so the
+    # relative agreement is ~1e-9 near convergence)
+    assert rg["rel_kkt"] == pytest.approx(k["rel_kkt"], rel=1e-7, abs=1e-14)
+    assert rg["primal_obj"] == pytest.approx(k["primal_obj"], rel=1e-12, abs=1e-12)
+    if check_log:
+        assert len(lg) == len(lo)
+        for a, b in zip(lg, lo):
+            assert (a["total"], a["k"], a["candidate"], a["restarted"]) == \
+                (b["total"], b["k"], b["candidate"], b["restarted"])
+            assert a["r_cur"] == pytest.approx(b["r_cur"], rel=1e-6, abs=1e-12)
+            assert a["r_avg"] == pytest.approx(b["r_avg"], rel=1e-6, abs=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# tiny random config (n=100, m=50) to tolerance
+# ---------------------------------------------------------------------------
+def test_tiny_config_to_tolerance(orc, qpa):
+    qp = qpgen.tiny_random_qp(1)
+    o, g = _pair(orc, qpa, qp, eps=1e-6)
+    _assert_parity(orc, qp, o, g)
+    assert g[2]["status"] == 0 and g[2]["rel_kkt"] <= 1e-6
+
+
+@pytest.mark.parametrize("seed", list(range(1001, 1021)))
+def test_tiny_config_seed_sweep(orc, qpa, seed):
+    qp = qpgen.tiny_random_qp(seed)
+    o, g = _pair(orc, qpa, qp, eps=1e-6)
+    _assert_parity(orc, qp, o, g)
+
+
+# ---------------------------------------------------------------------------
+# operator norms: GPU power iteration vs the oracle's
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("maker", ["tiny", "large", "portfolio"])
+def test_power_iteration_norms(orc, qpa, maker):
+    qp = {"tiny": lambda: qpgen.tiny_random_qp(1),
+          "large": lambda: qpgen.large_random_qp(seed=2, n=30000, m=15000),
+          "portfolio": lambda: qpgen.portfolio_qp(seed=3, n_assets=20000, k=40)}[maker]()
+    nA, nQ = _norms(orc, qp)
+    with qpa.Solver(qp, qpa.Settings()) as s:
+        gA, gQ = s.norms()
+    assert gA == pytest.approx(nA, rel=1e-5)
+    assert gQ == pytest.approx(nQ, rel=1e-5)
+
+
+# ---------------------------------------------------------------------------
+# scaled large random QP and portfolio QP at a fixed iteration count
+# ---------------------------------------------------------------------------
+def test_large_random_scaled_fixed_iterations(orc, qpa):
+    qp = qpgen.large_random_qp(seed=2, n=30000, m=15000)
+    o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=640)
+    _assert_parity(orc, qp, o, g)
+
+
+def test_large_random_scaled_to_tolerance(orc, qpa):
+    qp = qpgen.large_random_qp(seed=22, n=4000, m=2000)
+    o, g = _pair(orc, qpa, qp, eps=1e-6)
+    _assert_parity(orc, qp, o, g)
+
+
+def test_portfolio_scaled_long_rows(orc, qpa):
+    """Budget row of 20000 nonzeros: chunked rows combined across workgroups."""
+    qp = qpgen.portfolio_qp(seed=3, n_assets=20000, k=40)
+    assert qp.a_rowptr[-1] - qp.a_rowptr[-2] > 2048
+    o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=512)
+    _assert_parity(orc, qp, o, g)
+
+
+def test_portfolio_family_member_to_tolerance(orc, qpa):
+    fam = qpgen.portfolio_family(seed=5, count=2)
+    qp = fam.instance(0)
+    o, g = _pair(orc, qpa, qp, eps=1e-6)
+    _assert_parity(orc, qp, o, g)
+
+
+def test_mpc_instance_to_tolerance(orc, qpa):
+    rng = np.random.default_rng([4, 2])
+    qp = qpgen.mpc_qp(rng, 36, 9, 4)
+    o, g = _pair(orc, qpa, qp, eps=1e-6)
+    _assert_parity(orc, qp, o, g)
+
+
+# ---------------------------------------------------------------------------
+# restart modes, evaluation cadences, graph vs direct launches, warm starts
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode,kw", [(1, {"fixed_K": 100}), (1, {"fixed_K": 37}),
+                                     (2, {}), (3, {"eps": 1e-4, "max_iter": 3000})])
+def test_restart_modes(orc, qpa, mode, kw):
+    qp = qpgen.tiny_random_qp(1)
+    args = dict(eps=1e-6)
+    args.update(kw)
+    o, g = _pair(orc, qpa, qp, mode=mode, **args)
+    _assert_parity(orc, qp, o, g)
+
+
+@pytest.mark.parametrize("check_every,max_iter", [(1, 50), (7, 300), (64, 300), (100, 277)])
+def test_cadence_and_partial_interval(orc, qpa, check_every, max_iter):
+    qp = qpgen.tiny_random_qp(3)
+    o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=max_iter, check_every=check_every)
+    _assert_parity(orc, qp, o, g)
+    assert g[2]["iterations"] == max_iter and g[2]["status"] == 1
+
+
+def test_graph_and_direct_launch_identical(qpa, orc):
+    qp = qpgen.tiny_random_qp(4)
+    nA, nQ = _norms(orc, qp)
+    out = []
+    for ug in (0, 1):
+        with qpa.Solver(qp, qpa.Settings(norm_A=nA, norm_Q=nQ, use_graph=ug)) as s:
+            out.append(s.solve())
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert out[0][2]["iterations"] == out[1][2]["iterations"]
+
+
+def test_repeat_solve_is_deterministic(qpa):
+    qp = qpgen.large_random_qp(seed=2, n=30000, m=15000)
+    with qpa.Solver(qp, qpa.Settings(eps=0.0, max_iter=256)) as s:
+        a = s.solve()
+        b = s.solve()
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_warm_start_paths(orc, qpa):
+    qp = qpgen.tiny_random_qp(1)
+    xs, ys, _, _ = orc.solve(qp, orc.OracleSettings(eps=1e-9))
+    rng = np.random.default_rng(0)
+    xw = xs + 1e-3 * rng.standard_normal(qp.n)
+    yw = ys + 1e-3 * rng.standard_normal(qp.m)
+    for fb in (1, 0):
+        o, g = _pair(orc, qpa, qp, eps=1e-6, x0=xw, y0=yw, omega0=2.0, warm_fallback=fb)
+        _assert_parity(orc, qp, o, g)
+        assert g[2]["used_warm_start"] == 1
+    # a bad warm start is rejected by the fallback test
+    o, g = _pair(orc, qpa, qp, eps=1e-6, x0=np.full(qp.n, 1e6), y0=np.zeros(qp.m))
+    _assert_parity(orc, qp, o, g)
+    assert g[2]["used_warm_start"] == 0
+    # warm start at the solution terminates before the first iteration
+    o, g = _pair(orc, qpa, qp, eps=1e-8, x0=xs, y0=ys)
+    _assert_parity(orc, qp, o, g)
+    assert g[2]["iterations"] == 0
+
+
+# ---------------------------------------------------------------------------
+# edge cases: no rows, empty rows, rows at/above the LDS block size, free and
+# one-sided bounds, equality-only, singular Q
+# ---------------------------------------------------------------------------
+def test_unconstrained_m0(orc, qpa):
+    rng = np.random.default_rng(11)
+    n = 300
+    G = rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.05)
+    Q = G @ G.T / n + np.eye(n)
+    qp = qp_refs.make_qp(Q, np.zeros((0, n)), rng.standard_normal(n), [], np.full(n, -np.inf),
+                         np.full(n, np.inf), [])
+    o, g = _pair(orc, qpa, qp, eps=1e-9)
+    _assert_parity(orc, qp, o, g)
+    np.testing.assert_allclose(g[0], np.linalg.solve(Q, -qp.c), rtol=1e-6, atol=1e-7)
+
+
+def test_row_lengths_around_block_size(orc, qpa):
+    """Rows with 0, 1, 2047, 2048, 2049, 4097 and 6000 nonzeros plus short rows."""
+    rng = np.random.default_rng(12)
+    n = 7000
+    lens = [0, 1, 2047, 2048, 2049, 5, 4097, 0, 6000, 3] + [7] * 300
+    rows, cols, vals = [], [], []
+    for i, L in enumerate(lens):
+        c = rng.choice(n, size=L, replace=False)
+        rows += [i] * L
+        cols += list(c)
+        vals += list(rng.standard_normal(L) / math.sqrt(max(L, 1)))
+    import scipy.sparse as sp
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(len(lens), n))
+    x0 = rng.uniform(0, 1, n)
+    b = A @ x0
+    rt = (rng.random(len(lens)) < 0.5).astype(np.uint8)
+    b[rt == 1] -= 0.1
+    q = rng.uniform(0.5, 2.0, n)
+    qp = qpgen.instances._make("rowlens", sp.diags(q), A, rng.standard_normal(n), b,
+                               np.where(rng.random(n) < 0.5, 0.0, -np.inf),
+                               np.where(rng.random(n) < 0.3, 2.0, np.inf), rt)
+    o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=300)
+    _assert_parity(orc, qp, o, g)
+
+
+def test_equality_only_and_singular_q(orc, qpa):
+    # rank-5 Q with every variable boxed (bounded, so an optimum exists)
+    for seed in range(3):
+        qp = qp_refs.random_tiny_qp(200 + seed, n=40, m=15, bounded_frac=1.0, eq_frac=1.0,
+                                    psd_rank=5)
+        o, g = _pair(orc, qpa, qp, eps=1e-7)
+        _assert_parity(orc, qp, o, g)
+
+
+def test_numerical_error_status(orc, qpa):
+    qp = qpgen.tiny_random_qp(1)
+    qp.c = qp.c.copy()
+    qp.c[3] = np.nan
+    o, g = _pair(orc, qpa, qp, norms=(6.0, 24.0))
+    assert o[2]["status"] == 3 and g[2]["status"] == 3
+
+
+def test_device_arrays_path(orc, qpa):
+    import torch
+    qp = qpgen.tiny_random_qp(1)
+    nA, nQ = _norms(orc, qp)
+    with qpa.Solver(qp, qpa.Settings(norm_A=nA, norm_Q=nQ), device_arrays=True) as s:
+        xg, yg, rg = s.solve()
+    assert isinstance(xg, torch.Tensor) and xg.is_cuda
+    with qpa.Solver(qp, qpa.Settings(norm_A=nA, norm_Q=nQ)) as s:
+        xh, yh, rh = s.solve()
+    np.testing.assert_array_equal(xg.cpu().numpy(), xh)
+    np.testing.assert_array_equal(yg.cpu().numpy(), yh)
+
+
+# ---------------------------------------------------------------------------
+# the full-size large random QP (n=1e6, m=5e5), in the benchmark's launch
+# configuration, at a fixed iteration count
+# ---------------------------------------------------------------------------
+def test_large_random_full_size(orc, qpa):
+    qp = qpgen.large_random_qp()
+    nA, _ = orc.norm_A(qp, 40, 1e-7)
+    nQ, _ = orc.norm_Q(qp, 40, 1e-7)
+    o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=64, norms=(nA, nQ))
+    _assert_parity(orc, qp, o, g)
