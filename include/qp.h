@@ -125,6 +125,9 @@ typedef struct {
                                 (direct launches, no graph); read with qp_get_profile */
     int32_t log_checks;      /* 1: record one qp_check_info per evaluation (qp_get_check_log) */
     int32_t device;          /* HIP device ordinal; default 0 */
+    int32_t panels_dual;     /* column panels of A for the dual phase: 0 = automatic,
+                                1 = unpanelled, 2/4/8 = panels pinned to XCD groups */
+    int32_t panels_primal;   /* same for P = [Q | -A'] in the primal phase */
 } qp_settings;
 
 typedef struct {
@@ -189,13 +192,29 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
 int qp_batch_solve(qp_handle *h, const qp_warm_start *ws_array, qp_result *res_array,
                    double *x_out, double *y_out);
 
+/* Replaces the operator norms used for the step sizes (host arrays): one value each
+ * for a single QP, one per instance for a batch.  NULL keeps the current values.
+ * Errors: QP_ERR_INVALID_ARGUMENT for negative values or ||A|| = ||Q|| = 0. */
+int qp_set_norms(qp_handle *h, const double *norm_A, const double *norm_Q);
+
+/* Batch handles: instances are grouped in four size classes by n_i + m_i
+ * (<= 256, <= 1024, <= 2048, larger), each solved by a team of 64, 128, 256 or 512
+ * threads (1-8 wavefronts) per instance.  qp_batch_autotune times every team size
+ * on up to `sample` instances of each class for `iters` iterations and keeps the
+ * fastest; threads_out[4] (nullable) receives the choice.  qp_batch_set_threads
+ * sets the four team sizes directly.  Both return QP_ERR_BATCH_MISMATCH on a
+ * single-QP handle. */
+int qp_batch_autotune(qp_handle *h, int32_t sample, int32_t iters, int32_t *threads_out);
+int qp_batch_set_threads(qp_handle *h, const int32_t *threads);
+
 /* Copies up to cap records of the last solve's evaluation log (settings.log_checks). */
 int qp_get_check_log(qp_handle *h, qp_check_info *buf, int64_t cap, int64_t *len);
 
 /* Kernel timings of the last solve run with settings.profile = 1. */
 int qp_get_profile(qp_handle *h, qp_profile *out);
 
-/* Norms in use by the handle. */
+/* Norms in use by the handle: one value each for a single QP, num_instances values
+ * each for a batch (caller-sized host arrays, nullable). */
 int qp_get_norms(qp_handle *h, double *norm_A, double *norm_Q);
 
 /* Changes c and/or b (same layout and mem_space as at create; NULL keeps the old

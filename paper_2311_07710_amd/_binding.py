@@ -47,7 +47,7 @@ class qp_settings(C.Structure):
                 ("norm_Q", C.c_double), ("power_iter_max", C.c_int32),
                 ("power_iter_rtol", C.c_double), ("warm_fallback", C.c_int32),
                 ("use_graph", C.c_int32), ("profile", C.c_int32), ("log_checks", C.c_int32),
-                ("device", C.c_int32)]
+                ("device", C.c_int32), ("panels_dual", C.c_int32), ("panels_primal", C.c_int32)]
 
 
 class qp_warm_start(C.Structure):
@@ -85,6 +85,9 @@ SIGNATURES = {
     "qp_get_profile": (C.c_int, [_vp, C.POINTER(qp_profile)]),
     "qp_get_norms": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "qp_update_vectors": (C.c_int, [_vp, _vp, _vp]),
+    "qp_set_norms": (C.c_int, [_vp, _vp, _vp]),
+    "qp_batch_autotune": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp]),
+    "qp_batch_set_threads": (C.c_int, [_vp, _vp]),
     "qp_free": (None, [_vp]),
     "qp_last_error": (C.c_char_p, []),
     "qp_version": (C.c_int, []),

@@ -25,11 +25,12 @@
 
 #include "../../include/qp.h"
 #include "qp_batch.h"
+#include "qp_host.h"
 #include "qp_internal.h"
 
 using namespace qpk;
 
-namespace {
+namespace qph {
 
 thread_local std::string g_err;
 
@@ -43,41 +44,20 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIPCHK(expr)                                                                        \
-    do {                                                                                    \
-        hipError_t _e = (expr);                                                             \
-        if (_e != hipSuccess)                                                               \
-            return fail(_e == hipErrorOutOfMemory ? QP_ERR_OUT_OF_MEMORY : QP_ERR_DEVICE,   \
-                        "%s failed: %s", #expr, hipGetErrorString(_e));                     \
-    } while (0)
+void clear_error() { g_err.clear(); }
 
 double now_s() {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-struct DevMem {
-    void *p = nullptr;
-    size_t bytes = 0;
-    ~DevMem() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    int alloc(size_t b) {
-        release();
-        bytes = b;
-        if (b == 0) return QP_OK;
-        hipError_t e = hipMalloc(&p, b);
-        if (e != hipSuccess) {
-            p = nullptr;
-            return fail(QP_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
-        }
-        return QP_OK;
-    }
-    template <class T> T *as() const { return (T *)p; }
-};
+}  // namespace qph
+
+using qph::DevMem;
+using qph::fail;
+using qph::now_s;
+
+namespace {
 
 struct HostPartition {
     std::vector<Block> blk;
@@ -265,9 +245,11 @@ void qp_default_settings(qp_settings *s) {
     s->profile = 0;
     s->log_checks = 0;
     s->device = 0;
+    s->panels_dual = 0;
+    s->panels_primal = 0;
 }
 
-const char *qp_last_error(void) { return g_err.c_str(); }
+const char *qp_last_error(void) { return qph::g_err.c_str(); }
 
 int qp_version(void) { return QP_ABI_VERSION; }
 
@@ -670,7 +652,7 @@ int qp_create(const qp_problem_desc *d, const qp_settings *settings, qp_handle *
         }
     }
     if (d->num_instances > 1) {
-        rc = qpb::create_batch(d, &h->set, &h->batch);
+        rc = qpb::create_batch(d, &h->set, h->stream, &h->batch);
     } else {
         if (d->mem_space == QP_MEM_DEVICE) rc = gather_single(d, hp);
         if (!rc) rc = create_single(d, h, hp);
@@ -694,7 +676,7 @@ int qp_create(const qp_problem_desc *d, const qp_settings *settings, qp_handle *
         return rc;
     }
     *out = h;
-    g_err.clear();
+    qph::clear_error();
     return QP_OK;
 }
 
@@ -725,6 +707,30 @@ int qp_update_vectors(qp_handle *h, const double *c, const double *b) {
     HIPCHK(hipMemcpy(hc.data(), h->c.p, h->n * 8, hipMemcpyDeviceToHost));
     if (h->m) HIPCHK(hipMemcpy(hb.data(), h->b.p, h->m * 8, hipMemcpyDeviceToHost));
     return set_vectors_host_stats(h, hc, hb);
+}
+
+int qp_set_norms(qp_handle *h, const double *norm_A, const double *norm_Q) {
+    if (!h) return fail(QP_ERR_INVALID_ARGUMENT, "null handle");
+    if (h->batch) return qpb::batch_set_norms(h->batch, norm_A, norm_Q);
+    const double a = norm_A ? norm_A[0] : h->norm_A, q = norm_Q ? norm_Q[0] : h->norm_Q;
+    if (!(a >= 0.0) || !(q >= 0.0) || !(a > 0.0 || q > 0.0))
+        return fail(QP_ERR_INVALID_ARGUMENT, "invalid norms");
+    h->norm_A = a;
+    h->norm_Q = q;
+    return QP_OK;
+}
+
+int qp_batch_autotune(qp_handle *h, int32_t sample, int32_t iters, int32_t *threads_out) {
+    if (!h) return fail(QP_ERR_INVALID_ARGUMENT, "null handle");
+    if (!h->batch) return fail(QP_ERR_BATCH_MISMATCH, "qp_batch_autotune needs a batch handle");
+    HIPCHK(hipSetDevice(h->device));
+    return qpb::batch_autotune(h->batch, &h->set, sample, iters, threads_out);
+}
+
+int qp_batch_set_threads(qp_handle *h, const int32_t *threads) {
+    if (!h || !threads) return fail(QP_ERR_INVALID_ARGUMENT, "null argument");
+    if (!h->batch) return fail(QP_ERR_BATCH_MISMATCH, "qp_batch_set_threads needs a batch handle");
+    return qpb::batch_set_threads(h->batch, threads);
 }
 
 int qp_get_check_log(qp_handle *h, qp_check_info *buf, int64_t cap, int64_t *len) {
@@ -892,7 +898,7 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
     if (x_out) HIPCHK(hipMemcpy(x_out, xs, n * 8, kind));
     if (y_out && m) HIPCHK(hipMemcpy(y_out, ys, m * 8, kind));
     fill_result(h, last, now_s() - t0, res);
-    g_err.clear();
+    qph::clear_error();
     return QP_OK;
 }
 

@@ -1,26 +1,1018 @@
-// qp_batch.hip -- batched rAPDHG (placeholder until the persistent kernel lands).
+// qp_batch.hip -- many independent small QPs solved by rAPDHG in one
+// persistent launch per size class (segment-CSR layout).
+//
+// Layout: instances are concatenated; A's row pointers are global offsets into
+// the concatenated nonzeros, column indices are local to the instance.  Each
+// instance also gets its own P_i = [Q_i | -A_i'] (local columns < n_i address
+// x, columns n_i + r address y_r), built on the host at create.
+//
+// Kernel: one workgroup (a "team" of NT threads = NT/64 wavefronts) per
+// instance.  Workgroups pop instance ids from an atomic queue ordered by
+// decreasing work, run the whole solve -- Algorithm 1 iterations, Sec. 5
+// relKKT evaluation every `interval` iterations, Sec. 6 restart / primal
+// weight / step sizes -- with workgroup barriers between the dual phase, the
+// primal phase and the evaluation, write the returned point and their final
+// state, and pop the next instance; every workgroup exits once the queue is
+// empty.  Rows are handled one per thread with sums in CSR order, so each row
+// sum is the same operation sequence as a sequential CSR product.  The team
+// size per size class is chosen by timing (qp_batch_autotune).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
 #include "qp_batch.h"
+#include "qp_decide.h"
+#include "qp_host.h"
+#include "qp_internal.h"
+
+using qph::DevMem;
+using qph::fail;
 
 namespace qpb {
 
-struct BatchData {
-    int dummy = 0;
+using namespace qpk;
+
+constexpr int NCLASS = 4;
+static const int32_t CLASS_LIMIT[NCLASS] = {256, 1024, 2048, 1 << 30};  // n_i + m_i upper bound
+static const int32_t THREAD_CHOICES[4] = {64, 128, 256, 512};
+
+struct BatchDev {
+    int32_t count;
+    const int32_t *var_off, *row_off;
+    const int32_t *a_rowptr, *a_col;
+    const double *a_val;
+    const int32_t *p_rowptr, *p_col;
+    const double *p_val;
+    const double *c, *b, *l, *u;
+    const uint8_t *rt;
+    const double *normA, *normQ, *b_inf, *c_inf, *omega0;
+    const uint8_t *has_x0, *has_y0;
+    const double *x0, *y0;
+    double *x, *xbar, *xt, *xmd0, *xmd1, *xrs, *y, *ybar, *yrs;
+    double *x_out, *y_out;
+    State *res;
+    const int32_t *order;
+    int32_t order_count;
+    int32_t *head;
+    const int64_t *clock0;
+    int64_t deadline_ticks;  // 0: no time limit
+    int32_t warm_fallback, any_warm;
 };
 
-extern "C" const char *qp_last_error(void);
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double bmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
-int create_batch(const qp_problem_desc *, const qp_settings *, BatchData **out) {
+template <int NT>
+__device__ void team_reduce(double *cv, int nv, int nmax_first, double *red /*[32][NT/64]*/) {
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int v = 0; v < nv; ++v) {
+        double x = cv[v];
+        const bool mx = v < nmax_first;
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double o = __shfl_xor(x, off, 64);
+            x = mx ? bmax(x, o) : x + o;
+        }
+        if (lane == 0) red[v * (NT / 64) + wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 0; v < nv; ++v) {
+            const bool mx = v < nmax_first;
+            double acc = red[v * (NT / 64)];
+            for (int w = 1; w < NT / 64; ++w) {
+                const double o = red[v * (NT / 64) + w];
+                acc = mx ? bmax(acc, o) : acc + o;
+            }
+            cv[v] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// KKT quantities of z = (x, y) and z-bar for one instance; results in thread 0's ra/rp
+template <int NT>
+__device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, const double *aval,
+                         const int32_t *prp, const int32_t *pcol, const double *pval,
+                         const double *c, const double *b, const double *l, const double *u,
+                         const uint8_t *rt, const double *x, const double *xbar,
+                         const double *xrs, const double *y, const double *ybar,
+                         const double *yrs, double *ra, double *rp, double *red) {
+    for (int v = 0; v < RA_NV; ++v) ra[v] = 0.0;
+    for (int i = threadIdx.x; i < m; i += NT) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int e = arp[i]; e < arp[i + 1]; ++e) {
+            const int cc = acol[e];
+            const double a = aval[e];
+            s0 = s0 + a * x[cc];
+            s1 = s1 + a * xbar[cc];
+        }
+        const double bi = b[i];
+        double r0 = s0 - bi, r1 = s1 - bi;
+        if (rt[i] == 1) {
+            r0 = (r0 < 0.0) ? -r0 : 0.0;
+            r1 = (r1 < 0.0) ? -r1 : 0.0;
+        }
+        ra[RA_RES0] = bmax(ra[RA_RES0], fabs(r0));
+        ra[RA_RES1] = bmax(ra[RA_RES1], fabs(r1));
+        ra[RA_AX0] = bmax(ra[RA_AX0], fabs(s0));
+        ra[RA_AX1] = bmax(ra[RA_AX1], fabs(s1));
+        const double yi = y[i], ybi = ybar[i], yr = yrs[i];
+        ra[RA_BY0] += bi * yi;
+        ra[RA_BY1] += bi * ybi;
+        const double d0 = yi - yr, d1 = ybi - yr;
+        ra[RA_DY0] += d0 * d0;
+        ra[RA_DY1] += d1 * d1;
+    }
+    team_reduce<NT>(ra, RA_NV, 4, red);
+    for (int v = 0; v < RP_NV; ++v) rp[v] = 0.0;
+    for (int j = threadIdx.x; j < n; j += NT) {
+        double q[2] = {0.0, 0.0}, na[2] = {0.0, 0.0};
+        for (int e = prp[j]; e < prp[j + 1]; ++e) {
+            const int cc = pcol[e];
+            const double a = pval[e];
+            if (cc < n) {
+                q[0] = q[0] + a * x[cc];
+                q[1] = q[1] + a * xbar[cc];
+            } else {
+                na[0] = na[0] + a * y[cc - n];
+                na[1] = na[1] + a * ybar[cc - n];
+            }
+        }
+        const double cj = c[j], lj = l[j], uj = u[j];
+        const bool lo_fin = isfinite(lj), hi_fin = isfinite(uj);
+        for (int p = 0; p < 2; ++p) {
+            const double xp = p == 0 ? x[j] : xbar[j];
+            const double aty = -na[p];
+            const double lam = q[p] + cj - aty;
+            double lam_hat;
+            if (lo_fin && hi_fin) lam_hat = lam;
+            else if (lo_fin) lam_hat = lam > 0.0 ? lam : 0.0;
+            else if (hi_fin) lam_hat = lam < 0.0 ? lam : 0.0;
+            else lam_hat = 0.0;
+            rp[RP_DRES0 + p] = bmax(rp[RP_DRES0 + p], fabs(lam - lam_hat));
+            rp[RP_QX0 + p] = bmax(rp[RP_QX0 + p], fabs(q[p]));
+            rp[RP_ATY0 + p] = bmax(rp[RP_ATY0 + p], fabs(aty));
+            rp[RP_XQX0 + p] += xp * q[p];
+            rp[RP_CX0 + p] += cj * xp;
+            double bnd = 0.0;
+            if (lo_fin && lam_hat > 0.0) bnd = lj * lam_hat;
+            if (hi_fin && lam_hat < 0.0) bnd = uj * lam_hat;
+            rp[RP_BND0 + p] += bnd;
+            const double dx = xp - xrs[j];
+            rp[RP_DX0 + p] += dx * dx;
+        }
+    }
+    team_reduce<NT>(rp, RP_NV, 6, red);
+}
+
+// The evaluation logic is called out of line: inlined, its exp/log/sqrt code would
+// set the register budget (and so the occupancy) of the whole iteration loop.
+__device__ __attribute__((noinline)) void batch_decide(int mode, const double *ra,
+                                                       const double *rp, State *S,
+                                                       const DevSettings *ds, int32_t len) {
+    decide_update(mode, ra, rp, *S, *ds, len);
+}
+
+__device__ __forceinline__ double proj_box_b(double v, double lo, double hi) {
+    if (v < lo) v = lo;
+    if (v > hi) v = hi;
+    return v;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
+    __shared__ int s_q;
+    __shared__ State S;
+    __shared__ Step stp[2];
+    __shared__ double red[32 * (NT / 64)];
+    __shared__ double s_last;
+    const int t = threadIdx.x;
+    for (;;) {
+        if (t == 0) s_q = atomicAdd(a.head, 1);
+        __syncthreads();
+        const int q = s_q;
+        if (q >= a.order_count) break;
+        const int id = a.order[q];
+        const int v0 = a.var_off[id], n = a.var_off[id + 1] - v0;
+        const int r0 = a.row_off[id], m = a.row_off[id + 1] - r0;
+        const int32_t *arp = a.a_rowptr + r0;
+        const int32_t *prp = a.p_rowptr + v0;
+        const double *c = a.c + v0, *l = a.l + v0, *u = a.u + v0, *b = a.b + r0;
+        const uint8_t *rt = a.rt + r0;
+        double *x = a.x + v0, *xbar = a.xbar + v0, *xt = a.xt + v0, *xrs = a.xrs + v0;
+        double *xmd[2] = {a.xmd0 + v0, a.xmd1 + v0};
+        double *y = a.y + r0, *ybar = a.ybar + r0, *yrs = a.yrs + r0;
+        DevSettings ds = base;
+        ds.norm_A = a.normA[id];
+        ds.norm_Q = a.normQ[id];
+        ds.b_inf = a.b_inf[id];
+        ds.c_inf = a.c_inf[id];
+        const bool warm = a.any_warm && (a.has_x0[id] || a.has_y0[id]);
+        const bool pair = warm && a.warm_fallback;
+        // initial point (zeros or the warm start, projected); with the fallback the
+        // warm point sits in (x, y) and the cold one in (x-bar, y-bar)
+        for (int j = t; j < n; j += NT) {
+            const double xc = proj_box_b(0.0, l[j], u[j]);
+            const double xw = (warm && a.has_x0[id]) ? proj_box_b(a.x0[v0 + j], l[j], u[j]) : xc;
+            x[j] = xw;
+            xbar[j] = pair ? xc : xw;
+            xt[j] = xw;
+            xmd[0][j] = xw;
+            xrs[j] = xw;
+        }
+        for (int i = t; i < m; i += NT) {
+            double yw = (warm && a.has_y0[id]) ? a.y0[r0 + i] : 0.0;
+            if (rt[i] == 1 && yw < 0.0) yw = 0.0;
+            y[i] = yw;
+            ybar[i] = pair ? 0.0 : yw;
+            yrs[i] = yw;
+        }
+        if (t == 0) {
+            S.omega = a.omega0[id];
+            S.r0 = 0.0;
+            S.prev_cand = INFINITY;
+            S.s_last = 0.0;
+            S.r_cur = S.r_avg = 0.0;
+            S.total = S.k = S.restarts = S.kkt_evals = 0;
+            S.done = 0;
+            S.status = -1;
+            S.cand = 0;
+            S.restart_flag = 0;
+            S.used_warm = (warm && !pair) ? 1 : 0;
+            S.checks = 0;
+        }
+        __syncthreads();
+        double ra[RA_NV], rp[RP_NV];
+        if (pair) {
+            team_kkt<NT>(n, m, arp, a.a_col, a.a_val, prp, a.p_col, a.p_val, c, b, l, u, rt, x,
+                         xbar, xrs, y, ybar, yrs, ra, rp, red);
+            if (t == 0) batch_decide(DECIDE_FALLBACK, ra, rp, &S, &ds, 0);
+            __syncthreads();
+            const int take = S.used_warm;
+            for (int j = t; j < n; j += NT) {
+                const double xv = take ? x[j] : xbar[j];
+                x[j] = xbar[j] = xt[j] = xmd[0][j] = xrs[j] = xv;
+            }
+            for (int i = t; i < m; i += NT) {
+                const double yv = take ? y[i] : ybar[i];
+                y[i] = ybar[i] = yrs[i] = yv;
+            }
+            __syncthreads();
+        }
+        team_kkt<NT>(n, m, arp, a.a_col, a.a_val, prp, a.p_col, a.p_val, c, b, l, u, rt, x, xbar,
+                     xrs, y, ybar, yrs, ra, rp, red);
+        if (t == 0) {
+            batch_decide(DECIDE_INIT, ra, rp, &S, &ds, 0);
+            double sl = 0.0;
+            stp[0] = make_step(ds, S.omega, 0, &sl);
+            s_last = sl;
+        }
+        __syncthreads();
+        int sp = 0, md = 0;
+        while (!S.done) {
+            const int64_t left = ds.max_iter - S.total;
+            const int len = (int)(left < ds.interval ? left : ds.interval);
+            const int64_t k0 = S.k;
+            for (int j = 0; j < len; ++j) {
+                const Step st = stp[sp];
+                // dual phase: y+ = proj_Y(y - d (A x~ - b)), y-bar averaging
+                for (int i = t; i < m; i += NT) {
+                    double s = 0.0;
+                    for (int e = arp[i]; e < arp[i + 1]; ++e) {
+                        const double prod = a.a_val[e] * xt[a.a_col[e]];
+                        s = s + prod;
+                    }
+                    double yn = y[i] - st.d * (s - b[i]);
+                    if (rt[i] == 1 && yn < 0.0) yn = 0.0;
+                    ybar[i] = (1.0 - st.w) * ybar[i] + st.w * yn;
+                    y[i] = yn;
+                }
+                __syncthreads();
+                // primal phase over P = [Q | -A'] gathering (x_md, y+)
+                const double *xin = xmd[md];
+                double *xout = xmd[md ^ 1];
+                for (int jj = t; jj < n; jj += NT) {
+                    double s = 0.0;
+                    for (int e = prp[jj]; e < prp[jj + 1]; ++e) {
+                        const int cc = a.p_col[e];
+                        const double v = cc < n ? xin[cc] : y[cc - n];
+                        const double prod = a.p_val[e] * v;
+                        s = s + prod;
+                    }
+                    const double g = s + c[jj];
+                    const double xo = x[jj];
+                    double xn = xo - st.p * g;
+                    if (xn < l[jj]) xn = l[jj];
+                    if (xn > u[jj]) xn = u[jj];
+                    const double xb = (1.0 - st.w) * xbar[jj] + st.w * xn;
+                    x[jj] = xn;
+                    xbar[jj] = xb;
+                    xt[jj] = xn + st.theta_next * (xn - xo);
+                    xout[jj] = (1.0 - st.w_next) * xb + st.w_next * xn;
+                }
+                if (t == 0) {
+                    double sl = s_last;
+                    stp[sp ^ 1] = make_step(ds, S.omega, k0 + j + 1, &sl);
+                    s_last = sl;
+                }
+                __syncthreads();
+                sp ^= 1;
+                md ^= 1;
+            }
+            team_kkt<NT>(n, m, arp, a.a_col, a.a_val, prp, a.p_col, a.p_val, c, b, l, u, rt, x,
+                         xbar, xrs, y, ybar, yrs, ra, rp, red);
+            if (t == 0) {
+                batch_decide(DECIDE_CHECK, ra, rp, &S, &ds, len);
+                if (!S.done && a.deadline_ticks > 0 &&
+                    (int64_t)wall_clock64() - *a.clock0 >= a.deadline_ticks) {
+                    S.status = ST_TIME_LIMIT;
+                    S.done = 1;
+                    S.restart_flag = 0;
+                }
+                if (S.restart_flag) {
+                    double sl = 0.0;
+                    stp[sp] = make_step(ds, S.omega, 0, &sl);
+                    s_last = sl;
+                }
+            }
+            __syncthreads();
+            if (S.restart_flag) {
+                const int avg = S.cand;
+                for (int j = t; j < n; j += NT) {
+                    const double xc = avg ? xbar[j] : x[j];
+                    x[j] = xbar[j] = xt[j] = xmd[md][j] = xrs[j] = xc;
+                }
+                for (int i = t; i < m; i += NT) {
+                    const double yc = avg ? ybar[i] : y[i];
+                    y[i] = ybar[i] = yrs[i] = yc;
+                }
+                __syncthreads();
+            }
+        }
+        // the returned point: the candidate of the last evaluation
+        const int avg = S.cand;
+        for (int j = t; j < n; j += NT) a.x_out[v0 + j] = avg ? xbar[j] : x[j];
+        for (int i = t; i < m; i += NT) a.y_out[r0 + i] = avg ? ybar[i] : y[i];
+        if (t == 0) a.res[id] = S;
+        __syncthreads();
+    }
+}
+
+// power iteration per instance (same iteration as the single-instance path)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch_norms(BatchDev a, int32_t maxit, double rtol,
+                                                    double *outA, double *outQ) {
+    __shared__ int s_q;
+    __shared__ double red[32 * (NT / 64)];
+    __shared__ double s_val[2];
+    const int t = threadIdx.x;
+    for (;;) {
+        if (t == 0) s_q = atomicAdd(a.head, 1);
+        __syncthreads();
+        const int q = s_q;
+        if (q >= a.order_count) break;
+        const int id = a.order[q];
+        const int v0 = a.var_off[id], n = a.var_off[id + 1] - v0;
+        const int r0 = a.row_off[id], m = a.row_off[id + 1] - r0;
+        const int32_t *arp = a.a_rowptr + r0;
+        const int32_t *prp = a.p_rowptr + v0;
+        double *v = a.xbar + v0, *z = a.xt + v0, *w = a.ybar + r0;
+        double lam = 0.0;
+        // ||A||_2: Rayleigh quotient of A'A
+        if (m > 0 && arp[m] > arp[0]) {
+            for (int j = t; j < n; j += NT) v[j] = 1.0 / sqrt((double)n);
+            __syncthreads();
+            double lam_prev = 0.0;
+            for (int it = 1; it <= maxit; ++it) {
+                double acc[2] = {0.0, 0.0};
+                for (int i = t; i < m; i += NT) {
+                    double s = 0.0;
+                    for (int e = arp[i]; e < arp[i + 1]; ++e) s = s + a.a_val[e] * v[a.a_col[e]];
+                    w[i] = s;
+                    acc[0] += s * s;
+                }
+                team_reduce<NT>(acc, 1, 0, red);
+                if (t == 0) s_val[0] = acc[0];
+                __syncthreads();
+                lam = s_val[0];
+                acc[0] = 0.0;
+                for (int j = t; j < n; j += NT) {
+                    double s = 0.0;
+                    for (int e = prp[j]; e < prp[j + 1]; ++e) {
+                        const int cc = a.p_col[e];
+                        if (cc >= n) s = s + (-1.0) * (a.p_val[e] * w[cc - n]);
+                    }
+                    z[j] = s;
+                    acc[0] += s * s;
+                }
+                team_reduce<NT>(acc, 1, 0, red);
+                if (t == 0) s_val[1] = sqrt(acc[0]);
+                __syncthreads();
+                const double nz = s_val[1];
+                if (nz == 0.0) break;
+                for (int j = t; j < n; j += NT) v[j] = z[j] / nz;
+                __syncthreads();
+                if (it > 1 && fabs(lam - lam_prev) <= rtol * lam) break;
+                lam_prev = lam;
+            }
+        }
+        if (t == 0) outA[id] = sqrt(lam);
+        // ||Q||_2: Rayleigh quotient of Q
+        lam = 0.0;
+        for (int j = t; j < n; j += NT) v[j] = 1.0 / sqrt((double)n);
+        __syncthreads();
+        double lam_prev = 0.0;
+        for (int it = 1; it <= maxit; ++it) {
+            double acc[2] = {0.0, 0.0};
+            for (int j = t; j < n; j += NT) {
+                double s = 0.0;
+                for (int e = prp[j]; e < prp[j + 1]; ++e) {
+                    const int cc = a.p_col[e];
+                    if (cc < n) s = s + a.p_val[e] * v[cc];
+                }
+                z[j] = s;
+                acc[0] += v[j] * s;
+                acc[1] += s * s;
+            }
+            team_reduce<NT>(acc, 2, 0, red);
+            if (t == 0) {
+                s_val[0] = acc[0];
+                s_val[1] = sqrt(acc[1]);
+            }
+            __syncthreads();
+            lam = s_val[0];
+            const double nw = s_val[1];
+            if (nw == 0.0) break;
+            for (int j = t; j < n; j += NT) v[j] = z[j] / nw;
+            __syncthreads();
+            if (it > 1 && fabs(lam - lam_prev) <= rtol * fabs(lam)) break;
+            lam_prev = lam;
+        }
+        if (t == 0) outQ[id] = fabs(lam);
+        __syncthreads();
+    }
+}
+
+__global__ void k_queue_reset(int32_t *head, int64_t *clock0) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *head = 0;
+        *clock0 = (int64_t)wall_clock64();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct BatchData {
+    int32_t B = 0;
+    int64_t ntot = 0, mtot = 0;
+    hipStream_t stream = nullptr;
+    std::vector<int64_t> var_off, row_off;
+    std::vector<double> normA, normQ, c_norm2, b_norm2, c_inf, b_inf;
+    std::vector<int32_t> cls;                 // size class of each instance
+    std::vector<std::vector<int32_t>> order;  // per class, by decreasing work
+    int32_t threads[NCLASS] = {64, 128, 256, 512};
+    DevMem var_off_d, row_off_d, a_rowptr, a_col, a_val, p_rowptr, p_col, p_val;
+    DevMem c, b, l, u, rt, normA_d, normQ_d, b_inf_d, c_inf_d, omega0_d, has_x0, has_y0, x0, y0;
+    DevMem x, xbar, xt, xmd0, xmd1, xrs, y, ybar, yrs, x_out, y_out, res, order_d, head, clock0;
+    std::vector<int32_t> order_off;  // offsets of each class in order_d
+    std::vector<double> h_omega;     // staging of per-solve scalars (outlive async copies)
+    std::vector<uint8_t> h_hx, h_hy;
+    int wall_khz = 100000;
+    int num_cu = 256;
+};
+
+static int class_of(int64_t rows) {
+    for (int k = 0; k < NCLASS; ++k)
+        if (rows <= CLASS_LIMIT[k]) return k;
+    return NCLASS - 1;
+}
+
+static BatchDev make_dev(BatchData *bd) {
+    BatchDev a;
+    std::memset(&a, 0, sizeof(a));
+    a.count = bd->B;
+    a.var_off = bd->var_off_d.as<int32_t>();
+    a.row_off = bd->row_off_d.as<int32_t>();
+    a.a_rowptr = bd->a_rowptr.as<int32_t>();
+    a.a_col = bd->a_col.as<int32_t>();
+    a.a_val = bd->a_val.as<double>();
+    a.p_rowptr = bd->p_rowptr.as<int32_t>();
+    a.p_col = bd->p_col.as<int32_t>();
+    a.p_val = bd->p_val.as<double>();
+    a.c = bd->c.as<double>();
+    a.b = bd->b.as<double>();
+    a.l = bd->l.as<double>();
+    a.u = bd->u.as<double>();
+    a.rt = bd->rt.as<uint8_t>();
+    a.normA = bd->normA_d.as<double>();
+    a.normQ = bd->normQ_d.as<double>();
+    a.b_inf = bd->b_inf_d.as<double>();
+    a.c_inf = bd->c_inf_d.as<double>();
+    a.omega0 = bd->omega0_d.as<double>();
+    a.has_x0 = bd->has_x0.as<uint8_t>();
+    a.has_y0 = bd->has_y0.as<uint8_t>();
+    a.x0 = bd->x0.as<double>();
+    a.y0 = bd->y0.as<double>();
+    a.x = bd->x.as<double>();
+    a.xbar = bd->xbar.as<double>();
+    a.xt = bd->xt.as<double>();
+    a.xmd0 = bd->xmd0.as<double>();
+    a.xmd1 = bd->xmd1.as<double>();
+    a.xrs = bd->xrs.as<double>();
+    a.y = bd->y.as<double>();
+    a.ybar = bd->ybar.as<double>();
+    a.yrs = bd->yrs.as<double>();
+    a.x_out = bd->x_out.as<double>();
+    a.y_out = bd->y_out.as<double>();
+    a.res = bd->res.as<State>();
+    a.head = bd->head.as<int32_t>();
+    a.clock0 = bd->clock0.as<int64_t>();
+    return a;
+}
+
+template <class K>
+static int persistent_grid(K kernel, int nt, int count, int num_cu) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    int g = per_cu * num_cu;
+    return g < count ? g : count;
+}
+
+// launches one persistent kernel over the instances order[lo, hi)
+static void launch_class(BatchData *bd, BatchDev a, const DevSettings &ds, int nt, int lo, int hi,
+                         bool norms, int32_t maxit, double rtol) {
+    a.order = bd->order_d.as<int32_t>() + lo;
+    a.order_count = hi - lo;
+    if (a.order_count <= 0) return;
+    hipStream_t s = bd->stream;
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, a.head,
+                       (int64_t *)bd->clock0.p);
+#define QPB_LAUNCH(NT)                                                                           \
+    do {                                                                                         \
+        if (norms) {                                                                             \
+            int g = persistent_grid(k_batch_norms<NT>, NT, a.order_count, bd->num_cu);           \
+            hipLaunchKernelGGL(k_batch_norms<NT>, dim3(g), dim3(NT), 0, s, a, maxit, rtol,       \
+                               bd->normA_d.as<double>(), bd->normQ_d.as<double>());              \
+        } else {                                                                                 \
+            int g = persistent_grid(k_batch<NT>, NT, a.order_count, bd->num_cu);                 \
+            hipLaunchKernelGGL(k_batch<NT>, dim3(g), dim3(NT), 0, s, a, ds);                     \
+        }                                                                                        \
+    } while (0)
+    switch (nt) {
+    case 64: QPB_LAUNCH(64); break;
+    case 128: QPB_LAUNCH(128); break;
+    case 256: QPB_LAUNCH(256); break;
+    default: QPB_LAUNCH(512); break;
+    }
+#undef QPB_LAUNCH
+}
+
+static DevSettings batch_settings(const qp_settings *s) {
+    DevSettings ds;
+    std::memset(&ds, 0, sizeof(ds));
+    ds.eps = s->eps;
+    ds.beta_sufficient = s->beta_sufficient;
+    ds.beta_necessary = s->beta_necessary;
+    ds.beta_artificial = s->beta_artificial;
+    ds.pw_smoothing = s->pw_smoothing;
+    ds.eps_zero = s->eps_zero;
+    ds.step_safety = s->step_safety;
+    ds.max_iter = s->max_iter;
+    ds.restart_mode = s->restart_mode;
+    ds.fixed_K = s->fixed_K;
+    ds.interval = s->restart_mode == QP_RESTART_FIXED_K ? s->fixed_K : s->check_every;
+    return ds;
+}
+
+template <class T>
+static int fetch_vec(std::vector<T> &dst, const T *src, int64_t count, int ms) {
+    dst.resize((size_t)count);
+    if (count == 0) return QP_OK;
+    if (!src) return fail(QP_ERR_INVALID_ARGUMENT, "missing batch array");
+    if (ms == QP_MEM_HOST) std::memcpy(dst.data(), src, (size_t)count * sizeof(T));
+    else HIPCHK(hipMemcpy(dst.data(), src, (size_t)count * sizeof(T), hipMemcpyDeviceToHost));
+    return QP_OK;
+}
+
+static void vector_stats(BatchData *bd, const std::vector<double> &c, const std::vector<double> &b) {
+    for (int i = 0; i < bd->B; ++i) {
+        double cn = 0.0, ci = 0.0, bn = 0.0, bi = 0.0;
+        for (int64_t j = bd->var_off[i]; j < bd->var_off[i + 1]; ++j) {
+            cn += c[j] * c[j];
+            if (std::fabs(c[j]) > ci) ci = std::fabs(c[j]);
+        }
+        for (int64_t r = bd->row_off[i]; r < bd->row_off[i + 1]; ++r) {
+            bn += b[r] * b[r];
+            if (std::fabs(b[r]) > bi) bi = std::fabs(b[r]);
+        }
+        bd->c_norm2[i] = std::sqrt(cn);
+        bd->b_norm2[i] = std::sqrt(bn);
+        bd->c_inf[i] = ci;
+        bd->b_inf[i] = bi;
+    }
+}
+
+int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t stream,
+                 BatchData **out) {
     *out = nullptr;
-    return QP_ERR_UNSUPPORTED;
+    if (!d->var_off || !d->row_off)
+        return fail(QP_ERR_INVALID_ARGUMENT, "batch problems need var_off and row_off");
+    const int32_t B = d->num_instances;
+    const int ms = d->mem_space;
+    BatchData *bd = new BatchData();
+    bd->B = B;
+    bd->stream = stream;
+    bd->var_off.assign(d->var_off, d->var_off + B + 1);
+    bd->row_off.assign(d->row_off, d->row_off + B + 1);
+    auto bad = [&](int code, const char *msg) {
+        delete bd;
+        return fail(code, "%s", msg);
+    };
+    if (bd->var_off[0] != 0 || bd->row_off[0] != 0 || bd->var_off[B] != d->n ||
+        bd->row_off[B] != d->m)
+        return bad(QP_ERR_BATCH_MISMATCH, "var_off/row_off do not span [0,n) and [0,m)");
+    for (int i = 0; i < B; ++i)
+        if (bd->var_off[i + 1] <= bd->var_off[i] || bd->row_off[i + 1] < bd->row_off[i])
+            return bad(QP_ERR_BATCH_MISMATCH, "every instance needs n_i > 0 and m_i >= 0");
+    const int64_t n = d->n, m = d->m;
+    if (n + m >= ((int64_t)1 << 31)) return bad(QP_ERR_INVALID_ARGUMENT, "batch exceeds int32");
+    bd->ntot = n;
+    bd->mtot = m;
+    std::vector<int32_t> qr, qc, ar, ac;
+    std::vector<double> qv, av, c, b, l, u;
+    std::vector<uint8_t> rt;
+    int rc;
+    if ((rc = fetch_vec(qr, d->Q.row_ptr, n + 1, ms)) || (rc = fetch_vec(qc, d->Q.col_idx, d->Q.nnz, ms)) ||
+        (rc = fetch_vec(qv, d->Q.val, d->Q.nnz, ms)) || (rc = fetch_vec(c, d->c, n, ms))) {
+        delete bd;
+        return rc;
+    }
+    if (m > 0) {
+        if ((rc = fetch_vec(ar, d->A.row_ptr, m + 1, ms)) ||
+            (rc = fetch_vec(ac, d->A.col_idx, d->A.nnz, ms)) ||
+            (rc = fetch_vec(av, d->A.val, d->A.nnz, ms)) || (rc = fetch_vec(b, d->b, m, ms))) {
+            delete bd;
+            return rc;
+        }
+        if (d->row_type) {
+            if ((rc = fetch_vec(rt, d->row_type, m, ms))) {
+                delete bd;
+                return rc;
+            }
+        } else {
+            rt.assign(m, 0);
+        }
+    } else {
+        ar.assign(1, 0);
+    }
+    if (d->l) {
+        if ((rc = fetch_vec(l, d->l, n, ms))) { delete bd; return rc; }
+    } else {
+        l.assign(n, -INFINITY);
+    }
+    if (d->u) {
+        if ((rc = fetch_vec(u, d->u, n, ms))) { delete bd; return rc; }
+    } else {
+        u.assign(n, INFINITY);
+    }
+    // validation
+    if (qr[0] != 0 || qr[n] != d->Q.nnz || ar[0] != 0 || (m > 0 && ar[m] != d->A.nnz))
+        return bad(QP_ERR_INVALID_ARGUMENT, "row pointers do not match nnz");
+    for (int64_t j = 0; j < n; ++j)
+        if (qr[j + 1] < qr[j]) return bad(QP_ERR_INVALID_ARGUMENT, "Q.row_ptr decreases");
+    for (int64_t i = 0; i < m; ++i) {
+        if (ar[i + 1] < ar[i]) return bad(QP_ERR_INVALID_ARGUMENT, "A.row_ptr decreases");
+        if (rt[i] > 1) return bad(QP_ERR_INVALID_ARGUMENT, "row_type must be 0 or 1");
+    }
+    for (int64_t j = 0; j < n; ++j)
+        if (!(l[j] <= u[j]) || l[j] == INFINITY || u[j] == -INFINITY)
+            return bad(QP_ERR_INVALID_ARGUMENT, "invalid bounds");
+    const int64_t pnnz = d->Q.nnz + (m > 0 ? d->A.nnz : 0);
+    if (pnnz >= ((int64_t)1 << 31)) return bad(QP_ERR_INVALID_ARGUMENT, "batch exceeds int32");
+    std::vector<int32_t> pr(n + 1, 0), pc((size_t)pnnz);
+    std::vector<double> pv((size_t)pnnz);
+    {
+        std::vector<int64_t> acount(n, 0);
+        for (int i = 0; i < B; ++i) {
+            const int64_t nv = bd->var_off[i + 1] - bd->var_off[i];
+            for (int64_t r = bd->row_off[i]; r < bd->row_off[i + 1]; ++r)
+                for (int64_t e = ar[r]; e < ar[r + 1]; ++e) {
+                    if (ac[e] < 0 || ac[e] >= nv)
+                        return bad(QP_ERR_INVALID_ARGUMENT, "A column index outside its instance");
+                    acount[bd->var_off[i] + ac[e]]++;
+                }
+            for (int64_t j = bd->var_off[i]; j < bd->var_off[i + 1]; ++j)
+                for (int64_t e = qr[j]; e < qr[j + 1]; ++e)
+                    if (qc[e] < 0 || qc[e] >= nv)
+                        return bad(QP_ERR_INVALID_ARGUMENT, "Q column index outside its instance");
+        }
+        for (int64_t j = 0; j < n; ++j) pr[j + 1] = (int32_t)(pr[j] + (qr[j + 1] - qr[j]) + acount[j]);
+        std::vector<int64_t> next(n);
+        for (int64_t j = 0; j < n; ++j) {
+            int64_t pos = pr[j];
+            for (int64_t e = qr[j]; e < qr[j + 1]; ++e, ++pos) {
+                pc[pos] = qc[e];
+                pv[pos] = qv[e];
+            }
+            next[j] = pos;
+        }
+        for (int i = 0; i < B; ++i) {
+            const int64_t v0 = bd->var_off[i], r0 = bd->row_off[i];
+            const int64_t nv = bd->var_off[i + 1] - v0;
+            for (int64_t r = r0; r < bd->row_off[i + 1]; ++r)
+                for (int64_t e = ar[r]; e < ar[r + 1]; ++e) {
+                    const int64_t pos = next[v0 + ac[e]]++;
+                    pc[pos] = (int32_t)(nv + (r - r0));
+                    pv[pos] = -av[e];
+                }
+        }
+    }
+    std::vector<int32_t> vo(B + 1), ro(B + 1);
+    for (int i = 0; i <= B; ++i) {
+        vo[i] = (int32_t)bd->var_off[i];
+        ro[i] = (int32_t)bd->row_off[i];
+    }
+    const size_t nb = (size_t)n * 8, mb = (size_t)std::max<int64_t>(m, 1) * 8;
+    if ((rc = bd->var_off_d.upload(vo.data(), vo.size() * 4)) ||
+        (rc = bd->row_off_d.upload(ro.data(), ro.size() * 4)) ||
+        (rc = bd->a_rowptr.upload(ar.data(), ar.size() * 4)) ||
+        (rc = bd->a_col.upload(ac.data(), ac.size() * 4)) ||
+        (rc = bd->a_val.upload(av.data(), av.size() * 8)) ||
+        (rc = bd->p_rowptr.upload(pr.data(), pr.size() * 4)) ||
+        (rc = bd->p_col.upload(pc.data(), pc.size() * 4)) ||
+        (rc = bd->p_val.upload(pv.data(), pv.size() * 8)) || (rc = bd->c.upload(c.data(), nb)) ||
+        (rc = bd->b.upload(b.data(), b.size() * 8)) || (rc = bd->l.upload(l.data(), nb)) ||
+        (rc = bd->u.upload(u.data(), nb)) || (rc = bd->rt.upload(rt.data(), rt.size())) ||
+        (rc = bd->x.alloc(nb)) || (rc = bd->xbar.alloc(nb)) || (rc = bd->xt.alloc(nb)) ||
+        (rc = bd->xmd0.alloc(nb)) || (rc = bd->xmd1.alloc(nb)) || (rc = bd->xrs.alloc(nb)) ||
+        (rc = bd->y.alloc(mb)) || (rc = bd->ybar.alloc(mb)) || (rc = bd->yrs.alloc(mb)) ||
+        (rc = bd->x_out.alloc(nb)) || (rc = bd->y_out.alloc(mb)) || (rc = bd->x0.alloc(nb)) ||
+        (rc = bd->y0.alloc(mb)) || (rc = bd->res.alloc((size_t)B * sizeof(State))) ||
+        (rc = bd->head.alloc(8)) || (rc = bd->clock0.alloc(8)) ||
+        (rc = bd->normA_d.alloc((size_t)B * 8)) || (rc = bd->normQ_d.alloc((size_t)B * 8)) ||
+        (rc = bd->b_inf_d.alloc((size_t)B * 8)) || (rc = bd->c_inf_d.alloc((size_t)B * 8)) ||
+        (rc = bd->omega0_d.alloc((size_t)B * 8)) || (rc = bd->has_x0.alloc((size_t)B)) ||
+        (rc = bd->has_y0.alloc((size_t)B))) {
+        delete bd;
+        return rc;
+    }
+    bd->normA.assign(B, 0.0);
+    bd->normQ.assign(B, 0.0);
+    bd->c_norm2.assign(B, 0.0);
+    bd->b_norm2.assign(B, 0.0);
+    bd->c_inf.assign(B, 0.0);
+    bd->b_inf.assign(B, 0.0);
+    vector_stats(bd, c, b);
+    // size classes and queue order (decreasing nonzeros: long instances start first)
+    bd->cls.resize(B);
+    bd->order.assign(NCLASS, {});
+    std::vector<int64_t> work(B);
+    for (int i = 0; i < B; ++i) {
+        const int64_t rows = (bd->var_off[i + 1] - bd->var_off[i]) + (bd->row_off[i + 1] - bd->row_off[i]);
+        bd->cls[i] = class_of(rows);
+        work[i] = (pr[bd->var_off[i + 1]] - pr[bd->var_off[i]]) +
+                  (ar[bd->row_off[i + 1]] - ar[bd->row_off[i]]) + rows;
+        bd->order[bd->cls[i]].push_back(i);
+    }
+    std::vector<int32_t> flat;
+    bd->order_off.assign(NCLASS + 1, 0);
+    for (int k = 0; k < NCLASS; ++k) {
+        auto &o = bd->order[k];
+        std::stable_sort(o.begin(), o.end(), [&](int32_t p, int32_t q) { return work[p] > work[q]; });
+        flat.insert(flat.end(), o.begin(), o.end());
+        bd->order_off[k + 1] = (int32_t)flat.size();
+    }
+    if ((rc = bd->order_d.upload(flat.data(), flat.size() * 4))) {
+        delete bd;
+        return rc;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&bd->wall_khz, hipDeviceAttributeWallClockRate, dev);
+    (void)hipDeviceGetAttribute(&bd->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (bd->wall_khz <= 0) bd->wall_khz = 100000;
+    // operator norms: overrides, else a batched power iteration
+    if (s->norm_A > 0.0 && s->norm_Q > 0.0) {
+        bd->normA.assign(B, s->norm_A);
+        bd->normQ.assign(B, s->norm_Q);
+    } else {
+        BatchDev a = make_dev(bd);
+        DevSettings ds = batch_settings(s);
+        for (int k = 0; k < NCLASS; ++k)
+            launch_class(bd, a, ds, bd->threads[k], bd->order_off[k], bd->order_off[k + 1], true,
+                         s->power_iter_max, s->power_iter_rtol);
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            delete bd;
+            return fail(QP_ERR_DEVICE, "batched power iteration: %s", hipGetErrorString(e));
+        }
+        if (hipMemcpy(bd->normA.data(), bd->normA_d.p, (size_t)B * 8, hipMemcpyDeviceToHost) !=
+                hipSuccess ||
+            hipMemcpy(bd->normQ.data(), bd->normQ_d.p, (size_t)B * 8, hipMemcpyDeviceToHost) !=
+                hipSuccess) {
+            delete bd;
+            return fail(QP_ERR_DEVICE, "reading batched norms failed");
+        }
+        if (s->norm_A > 0.0) bd->normA.assign(B, s->norm_A);
+        if (s->norm_Q > 0.0) bd->normQ.assign(B, s->norm_Q);
+    }
+    for (int i = 0; i < B; ++i)
+        if (!(bd->normA[i] > 0.0) && !(bd->normQ[i] > 0.0)) {
+            delete bd;
+            return fail(QP_ERR_INVALID_ARGUMENT, "instance %d has ||A|| = ||Q|| = 0", i);
+        }
+    *out = bd;
+    return QP_OK;
 }
-void destroy_batch(BatchData *b) { delete b; }
-int batch_solve(BatchData *, const qp_settings *, int, const qp_warm_start *, qp_result *,
-                double *, double *) {
-    return QP_ERR_UNSUPPORTED;
+
+void destroy_batch(BatchData *b) {
+    if (b) {
+        (void)hipStreamSynchronize(b->stream);
+        delete b;
+    }
 }
-int batch_norms(BatchData *, double *, double *) { return QP_ERR_UNSUPPORTED; }
-int batch_update_vectors(BatchData *, const double *, const double *, int) {
-    return QP_ERR_UNSUPPORTED;
+
+int batch_norms(BatchData *b, double *norm_A, double *norm_Q) {
+    if (norm_A) std::memcpy(norm_A, b->normA.data(), (size_t)b->B * 8);
+    if (norm_Q) std::memcpy(norm_Q, b->normQ.data(), (size_t)b->B * 8);
+    return QP_OK;
+}
+
+int batch_set_norms(BatchData *b, const double *norm_A, const double *norm_Q) {
+    for (int i = 0; i < b->B; ++i) {
+        const double a = norm_A ? norm_A[i] : b->normA[i];
+        const double q = norm_Q ? norm_Q[i] : b->normQ[i];
+        if (!(a >= 0.0) || !(q >= 0.0) || !(a > 0.0 || q > 0.0))
+            return fail(QP_ERR_INVALID_ARGUMENT, "invalid norms for instance %d", i);
+    }
+    if (norm_A) std::memcpy(b->normA.data(), norm_A, (size_t)b->B * 8);
+    if (norm_Q) std::memcpy(b->normQ.data(), norm_Q, (size_t)b->B * 8);
+    return QP_OK;
+}
+
+int batch_update_vectors(BatchData *bd, const double *c, const double *bvec, int ms) {
+    const hipMemcpyKind kind = ms == QP_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    if (c) HIPCHK(hipMemcpy(bd->c.p, c, (size_t)bd->ntot * 8, kind));
+    if (bvec && bd->mtot) HIPCHK(hipMemcpy(bd->b.p, bvec, (size_t)bd->mtot * 8, kind));
+    std::vector<double> hc(bd->ntot), hb(bd->mtot);
+    HIPCHK(hipMemcpy(hc.data(), bd->c.p, (size_t)bd->ntot * 8, hipMemcpyDeviceToHost));
+    if (bd->mtot) HIPCHK(hipMemcpy(hb.data(), bd->b.p, (size_t)bd->mtot * 8, hipMemcpyDeviceToHost));
+    vector_stats(bd, hc, hb);
+    return QP_OK;
+}
+
+int batch_set_threads(BatchData *b, const int32_t *threads) {
+    for (int k = 0; k < NCLASS; ++k) {
+        const int32_t v = threads[k];
+        if (v != 64 && v != 128 && v != 256 && v != 512)
+            return fail(QP_ERR_INVALID_ARGUMENT, "threads per instance must be 64, 128, 256 or 512");
+    }
+    std::memcpy(b->threads, threads, sizeof(b->threads));
+    return QP_OK;
+}
+
+// uploads per-instance scalars and warm starts, runs every size class
+// max_count[k]: instances of class k to run (-1: all, 0: none)
+static int run_batch(BatchData *bd, const qp_settings *s, int ms, const qp_warm_start *ws,
+                     const int32_t *threads, const int32_t *max_count) {
+    const int B = bd->B;
+    hipStream_t st = bd->stream;
+    std::vector<double> &omega = bd->h_omega;
+    std::vector<uint8_t> &hx = bd->h_hx, &hy = bd->h_hy;
+    HIPCHK(hipStreamSynchronize(st));  // the staging vectors may still feed a previous solve
+    omega.assign(B, 0.0);
+    hx.assign(B, 0);
+    hy.assign(B, 0);
+    bool any_warm = false;
+    const hipMemcpyKind kind = ms == QP_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    for (int i = 0; i < B; ++i) {
+        const double w0 = ws ? ws[i].omega0 : 0.0;
+        omega[i] = w0 > 0.0 ? w0
+                   : (bd->c_norm2[i] > s->eps_zero && bd->b_norm2[i] > s->eps_zero)
+                       ? bd->c_norm2[i] / bd->b_norm2[i]
+                       : 1.0;
+        if (ws && ws[i].x0) {
+            const int64_t v0 = bd->var_off[i], nv = bd->var_off[i + 1] - v0;
+            HIPCHK(hipMemcpyAsync(bd->x0.as<double>() + v0, ws[i].x0, nv * 8, kind, st));
+            hx[i] = 1;
+            any_warm = true;
+        }
+        if (ws && ws[i].y0) {
+            const int64_t r0 = bd->row_off[i], nr = bd->row_off[i + 1] - r0;
+            if (nr > 0) HIPCHK(hipMemcpyAsync(bd->y0.as<double>() + r0, ws[i].y0, nr * 8, kind, st));
+            hy[i] = 1;
+            any_warm = true;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(bd->omega0_d.p, omega.data(), (size_t)B * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bd->has_x0.p, hx.data(), (size_t)B, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bd->has_y0.p, hy.data(), (size_t)B, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bd->normA_d.p, bd->normA.data(), (size_t)B * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bd->normQ_d.p, bd->normQ.data(), (size_t)B * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bd->b_inf_d.p, bd->b_inf.data(), (size_t)B * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bd->c_inf_d.p, bd->c_inf.data(), (size_t)B * 8, hipMemcpyHostToDevice, st));
+    BatchDev a = make_dev(bd);
+    a.warm_fallback = s->warm_fallback;
+    a.any_warm = any_warm ? 1 : 0;
+    a.deadline_ticks = s->time_limit_s > 0.0
+                           ? (int64_t)(s->time_limit_s * 1000.0 * (double)bd->wall_khz)
+                           : 0;
+    DevSettings ds = batch_settings(s);
+    for (int k = 0; k < NCLASS; ++k) {
+        int lo = bd->order_off[k], hi = bd->order_off[k + 1];
+        if (max_count && max_count[k] >= 0 && hi - lo > max_count[k]) hi = lo + max_count[k];
+        launch_class(bd, a, ds, threads[k], lo, hi, false, 0, 0.0);
+    }
+    HIPCHK(hipGetLastError());
+    return QP_OK;
+}
+
+int batch_solve(BatchData *bd, const qp_settings *s, int ms, const qp_warm_start *ws,
+                qp_result *res, double *x_out, double *y_out) {
+    const double t0 = qph::now_s();
+    int rc;
+    if ((rc = run_batch(bd, s, ms, ws, bd->threads, nullptr))) return rc;
+    HIPCHK(hipStreamSynchronize(bd->stream));
+    const double dt = qph::now_s() - t0;
+    std::vector<State> S(bd->B);
+    HIPCHK(hipMemcpy(S.data(), bd->res.p, (size_t)bd->B * sizeof(State), hipMemcpyDeviceToHost));
+    const hipMemcpyKind kind = ms == QP_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (x_out) HIPCHK(hipMemcpy(x_out, bd->x_out.p, (size_t)bd->ntot * 8, kind));
+    if (y_out && bd->mtot) HIPCHK(hipMemcpy(y_out, bd->y_out.p, (size_t)bd->mtot * 8, kind));
+    for (int i = 0; i < bd->B; ++i) {
+        qp_result &r = res[i];
+        std::memset(&r, 0, sizeof(r));
+        const State &Z = S[i];
+        r.status = Z.status;
+        r.used_warm_start = Z.used_warm;
+        r.iterations = Z.total;
+        r.restarts = Z.restarts;
+        r.kkt_evals = Z.kkt_evals;
+        const double *k = Z.kkt[Z.cand ? 1 : 0];
+        r.r_primal = k[0];
+        r.r_dual = k[1];
+        r.r_gap = k[2];
+        r.rel_kkt = k[3];
+        r.primal_obj = k[4];
+        r.dual_obj = k[5];
+        r.omega = Z.omega;
+        r.norm_A = bd->normA[i];
+        r.norm_Q = bd->normQ[i];
+        r.solve_time_s = dt;
+    }
+    return QP_OK;
+}
+
+int batch_autotune(BatchData *bd, const qp_settings *s, int32_t sample, int32_t iters,
+                   int32_t *threads_out) {
+    // fixed work per trial: `iters` iterations (eps = 0) on up to `sample` instances per class
+    qp_settings ts = *s;
+    ts.eps = 0.0;
+    ts.max_iter = iters > 0 ? iters : 256;
+    ts.time_limit_s = 0.0;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int32_t best[NCLASS];
+    std::memcpy(best, bd->threads, sizeof(best));
+    for (int k = 0; k < NCLASS; ++k) {
+        if (bd->order_off[k + 1] == bd->order_off[k]) continue;
+        float best_ms = 1e30f;
+        for (int c = 0; c < 4; ++c) {
+            int32_t thr[NCLASS], cnt[NCLASS];
+            for (int q = 0; q < NCLASS; ++q) {
+                thr[q] = THREAD_CHOICES[c];
+                cnt[q] = q == k ? (sample > 0 ? sample : -1) : 0;  // only class k runs
+            }
+            for (int rep = 0; rep < 2; ++rep) {  // the first pass warms up
+                HIPCHK(hipEventRecord(e0, bd->stream));
+                int rc = run_batch(bd, &ts, QP_MEM_HOST, nullptr, thr, cnt);
+                if (rc) return rc;
+                HIPCHK(hipEventRecord(e1, bd->stream));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (rep == 1 && ms < best_ms) {
+                    best_ms = ms;
+                    best[k] = THREAD_CHOICES[c];
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::memcpy(bd->threads, best, sizeof(best));
+    if (threads_out) std::memcpy(threads_out, best, sizeof(best));
+    return QP_OK;
 }
 
 }  // namespace qpb

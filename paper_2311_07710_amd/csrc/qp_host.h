@@ -1,0 +1,58 @@
+// qp_host.h -- host-side helpers shared by the single-instance and batched
+// solvers: thread-local error reporting, HIP error mapping, device buffers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "../../include/qp.h"
+
+namespace qph {
+
+// records a formatted message for qp_last_error() and returns `code`
+int fail(int code, const char *fmt, ...);
+void clear_error();
+double now_s();
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess)                                                                 \
+            return ::qph::fail(_e == hipErrorOutOfMemory ? QP_ERR_OUT_OF_MEMORY : QP_ERR_DEVICE, \
+                               "%s failed: %s", #expr, hipGetErrorString(_e));                \
+    } while (0)
+
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    int alloc(size_t b) {
+        release();
+        bytes = b;
+        if (b == 0) return QP_OK;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(QP_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
+        }
+        return QP_OK;
+    }
+    int upload(const void *src, size_t b) {
+        int rc = alloc(b < 8 ? 8 : b);
+        if (rc) return rc;
+        if (b) HIPCHK(hipMemcpy(p, src, b, hipMemcpyHostToDevice));
+        return QP_OK;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+}  // namespace qph

@@ -20,6 +20,7 @@
 // MFMA anywhere on this path.
 #include <math.h>
 
+#include "qp_decide.h"
 #include "qp_internal.h"
 
 namespace qpk {
@@ -467,57 +468,6 @@ __global__ __launch_bounds__(BS) void k_kkt_cols(Blocks bk, Csr P, KktColArgs a,
 // decision kernel (one workgroup): relKKT, candidate, restart, primal weight,
 // step table for the next interval
 // ---------------------------------------------------------------------------
-// Sec. 6 step-size cap at inner index k: 0.99 (k+2) / (||Q||/w + sqrt(||A||^2 (k+2)^2 + ||Q||^2/w^2))
-__device__ double pdqp_cap(const DevSettings &s, double omega, int64_t k) {
-    const double kk = (double)(k + 2);
-    const double qw = s.norm_Q / omega;
-    return s.step_safety * kk / (qw + sqrt(s.norm_A * s.norm_A * kk * kk + qw * qw));
-}
-
-__device__ void step_at(const DevSettings &s, double omega, int64_t k, double *s_last, double *p,
-                        double *d) {
-    if (s.restart_mode == MODE_FIXED_K) {  // Theorem 1 / eq. (param-choice)
-        const double Kf = (double)s.fixed_K;
-        *p = (double)(k + 1) / (2.0 * (s.norm_Q + Kf * s.norm_A));
-        *d = s.norm_A > 0.0 ? (double)(k + 1) / (2.0 * Kf * s.norm_A) : 0.0;
-        *s_last = 0.0;
-        return;
-    }
-    const double cap = pdqp_cap(s, omega, k);
-    double sk;
-    if (k == 0) {
-        sk = cap;
-    } else {
-        const double grown = (1.0 + 1.0 / (double)k) * (*s_last);
-        sk = grown < cap ? grown : cap;
-    }
-    *s_last = sk;
-    *p = sk / omega;
-    *d = sk * omega;
-}
-
-__device__ void rel_kkt_point(const double *ra, const double *rp, int p, const DevSettings &s,
-                              double *out) {
-    const double res_p = ra[RA_RES0 + p], ax = ra[RA_AX0 + p], by = ra[RA_BY0 + p];
-    const double dres = rp[RP_DRES0 + p], qx = rp[RP_QX0 + p], aty = rp[RP_ATY0 + p];
-    const double xqx = rp[RP_XQX0 + p], cx = rp[RP_CX0 + p], bnd = rp[RP_BND0 + p];
-    const double P = 0.5 * xqx + cx;
-    const double D = -0.5 * xqx + by + bnd;
-    const double r_p = res_p / (1.0 + fmax(ax, s.b_inf));
-    const double r_d = dres / (1.0 + fmax(fmax(qx, aty), s.c_inf));
-    const double r_g = fabs(P - D) / (1.0 + fmax(fabs(P), fabs(D)));
-    double r = r_p;
-    if (r_d > r) r = r_d;
-    if (r_g > r) r = r_g;
-    if (isnan(r_p) || isnan(r_d) || isnan(r_g)) r = NAN;
-    out[0] = r_p;
-    out[1] = r_d;
-    out[2] = r_g;
-    out[3] = r;
-    out[4] = P;
-    out[5] = D;
-}
-
 __global__ __launch_bounds__(BS) void k_decide(int mode, const double *__restrict__ partA,
                                                int32_t nslotA, const double *__restrict__ partP,
                                                int32_t nslotP, State *st, Step *table,
@@ -558,108 +508,11 @@ __global__ __launch_bounds__(BS) void k_decide(int mode, const double *__restric
     double ra[RA_NV], rp[RP_NV];
     for (int v = 0; v < RA_NV; ++v) ra[v] = red[v][0];
     for (int v = 0; v < RP_NV; ++v) rp[v] = red[RA_NV + v][0];
-    double k0[6], k1[6];
-    rel_kkt_point(ra, rp, 0, s, k0);
-    rel_kkt_point(ra, rp, 1, s, k1);
-
     State S = *st;
-    int restart = 0;
-    if (mode == DECIDE_FALLBACK) {
-        // point 0 = warm start, point 1 = cold start
-        S.used_warm = k0[3] < k1[3] ? 1 : 0;
-        S.kkt_evals += 2;
-        *st = S;
-        return;
-    }
-    if (mode == DECIDE_INIT) {
-        S.kkt_evals += 1;
-        S.r0 = k0[3];
-        S.prev_cand = INFINITY;
-        S.total = 0;
-        S.k = 0;
-        S.cand = 0;
-        S.r_cur = S.r_avg = k0[3];
-        for (int i = 0; i < 6; ++i) S.kkt[0][i] = S.kkt[1][i] = k0[i];
-        if (isnan(k0[3])) {
-            S.status = ST_NUMERICAL;
-            S.done = 1;
-        } else if (k0[3] <= s.eps) {
-            S.status = ST_OPTIMAL;
-            S.done = 1;
-        } else if (s.max_iter <= 0) {
-            S.status = ST_ITER_LIMIT;
-            S.done = 1;
-        }
-    } else {  // DECIDE_CHECK after `len` iterations
-        S.total += len;
-        S.k += len;
-        S.kkt_evals += 2;
-        S.checks += 1;
-        const double r = k0[3], rb = k1[3];
-        const bool fixed = s.restart_mode == MODE_FIXED_K;
-        int cand_avg = fixed ? 1 : !(r < rb);
-        double rc = cand_avg ? rb : r;
-        if (isnan(r) || isnan(rb)) {
-            S.status = ST_NUMERICAL;
-            S.done = 1;
-        } else if (rc <= s.eps) {
-            S.status = ST_OPTIMAL;
-            S.done = 1;
-        } else if (S.total >= s.max_iter) {
-            S.status = ST_ITER_LIMIT;
-            S.done = 1;
-        } else if (s.restart_mode == MODE_ADAPTIVE) {
-            restart = (rc <= s.beta_sufficient * S.r0) ||
-                      (rc <= s.beta_necessary * S.r0 && rc > S.prev_cand) ||
-                      ((double)S.k >= s.beta_artificial * (double)S.total);
-        } else if (s.restart_mode == MODE_HALVING) {
-            restart = rb <= 0.5 * S.r0;
-            if (restart) {
-                cand_avg = 1;
-                rc = rb;
-            }
-        } else if (fixed) {
-            restart = 1;
-        }
-        if (restart) {
-            if (!fixed) {  // Sec. 6 primal weight update
-                const double dx = sqrt(rp[RP_DX0 + cand_avg]);
-                const double dy = sqrt(ra[RA_DY0 + cand_avg]);
-                if (dx > s.eps_zero && dy > s.eps_zero)
-                    S.omega = exp(s.pw_smoothing * log(dy / dx) +
-                                  (1.0 - s.pw_smoothing) * log(S.omega));
-            }
-            S.k = 0;
-            S.r0 = rc;
-            S.prev_cand = INFINITY;
-            S.restarts += 1;
-        } else if (!S.done) {
-            S.prev_cand = rc;
-        }
-        S.cand = cand_avg;
-        S.r_cur = r;
-        S.r_avg = rb;
-        for (int i = 0; i < 6; ++i) {
-            S.kkt[0][i] = k0[i];
-            S.kkt[1][i] = k1[i];
-        }
-    }
-    S.restart_flag = restart;
-    if (!S.done) {
+    decide_update(mode, ra, rp, S, s, len);
+    if (mode != DECIDE_FALLBACK && !S.done) {
         double sl = S.s_last;
-        for (int j = 0; j < s.interval; ++j) {
-            const int64_t kj = S.k + j;
-            double p, d;
-            step_at(s, S.omega, kj, &sl, &p, &d);
-            Step e;
-            e.p = p;
-            e.d = d;
-            e.w = 2.0 / (double)(kj + 2);
-            e.theta_next = (double)(kj + 1) / (double)(kj + 2);
-            e.w_next = 2.0 / (double)(kj + 3);
-            e.pad[0] = e.pad[1] = e.pad[2] = 0.0;
-            table[j] = e;
-        }
+        for (int j = 0; j < s.interval; ++j) table[j] = make_step(s, S.omega, S.k + j, &sl);
         S.s_last = sl;
     }
     *st = S;

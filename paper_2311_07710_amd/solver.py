@@ -38,6 +38,8 @@ class Settings:
     profile: int = 0
     log_checks: int = 0
     device: int = 0
+    panels_dual: int = 0
+    panels_primal: int = 0
 
     def c_struct(self) -> B.qp_settings:
         s = B.qp_settings()
@@ -140,6 +142,10 @@ class Solver:
         B.check(self.lib.qp_get_norms(self.h, C.byref(a), C.byref(q)))
         return a.value, q.value
 
+    def set_norms(self, norm_A: float, norm_Q: float):
+        a, q = C.c_double(norm_A), C.c_double(norm_Q)
+        B.check(self.lib.qp_set_norms(self.h, C.byref(a), C.byref(q)))
+
     def update_vectors(self, c=None, b=None):
         keep = _Keep(self.device_arrays)
         B.check(self.lib.qp_update_vectors(self.h, keep.ptr(c, np.float64), keep.ptr(b, np.float64)))
@@ -205,6 +211,27 @@ class BatchSolver:
     def update_vectors(self, c=None, b=None):
         keep = _Keep(self.device_arrays)
         B.check(self.lib.qp_update_vectors(self.h, keep.ptr(c, np.float64), keep.ptr(b, np.float64)))
+
+    def norms(self):
+        a = np.zeros(self.count)
+        q = np.zeros(self.count)
+        B.check(self.lib.qp_get_norms(self.h, a.ctypes.data, q.ctypes.data))
+        return a, q
+
+    def set_norms(self, norm_A=None, norm_Q=None):
+        a = None if norm_A is None else np.ascontiguousarray(norm_A, dtype=np.float64)
+        q = None if norm_Q is None else np.ascontiguousarray(norm_Q, dtype=np.float64)
+        B.check(self.lib.qp_set_norms(self.h, a.ctypes.data if a is not None else None,
+                                      q.ctypes.data if q is not None else None))
+
+    def autotune(self, sample: int = 64, iters: int = 256):
+        out = np.zeros(4, dtype=np.int32)
+        B.check(self.lib.qp_batch_autotune(self.h, int(sample), int(iters), out.ctypes.data))
+        return [int(v) for v in out]
+
+    def set_threads(self, threads):
+        t = np.ascontiguousarray(threads, dtype=np.int32)
+        B.check(self.lib.qp_batch_set_threads(self.h, t.ctypes.data))
 
     def solve(self, x0=None, y0=None, omega0=None):
         """x0/y0: concatenated warm starts (or None); omega0: per-instance array or None."""

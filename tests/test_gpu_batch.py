@@ -1,0 +1,153 @@
+"""Batched persistent-kernel solver vs the CPU oracle, instance by instance.
+
+Each instance of the batch must reproduce a single-instance oracle run with the
+same norms and settings: equal status, iteration and restart counts, relKKT
+within 1e-8, objective within 1e-8 relative, iterates within 1e-8 relative.
+"""
+import numpy as np
+import pytest
+
+import qpgen
+from tests import qp_refs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qpa():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    import paper_2311_07710_amd as m
+    m.load()
+    return m
+
+
+def _mixed_batch():
+    insts = []
+    for i in range(10):                      # MPC instances of every size class
+        rng = np.random.default_rng([4, i])
+        T = int(rng.integers(10, 101)); nx = int(rng.integers(4, 13)); nu = int(rng.integers(2, 5))
+        insts.append(qpgen.mpc_qp(rng, T, nx, nu, name=f"mpc{i}"))
+    insts += [qpgen.tiny_random_qp(s) for s in (1, 2, 3)]
+    fam = qpgen.portfolio_family(seed=5, count=2)
+    insts.append(fam.instance(1))            # n + m = 5201: the largest class
+    rng = np.random.default_rng(9)          # an instance without constraint rows
+    n = 30
+    G = rng.standard_normal((n, n))
+    insts.append(qp_refs.make_qp(G @ G.T / n + np.eye(n), np.zeros((0, n)), rng.standard_normal(n),
+                                 [], np.full(n, -1.0), np.full(n, 1.0), []))
+    return insts
+
+
+def _oracle_all(orc, insts, eps, max_iter=200000, x0s=None, y0s=None, fb=1):
+    out = []
+    for i, qp in enumerate(insts):
+        nA, _ = orc.norm_A(qp, 1000, 1e-7)
+        nQ, _ = orc.norm_Q(qp, 1000, 1e-7)
+        s = orc.OracleSettings(eps=eps, max_iter=max_iter, norm_A=nA, norm_Q=nQ, warm_fallback=fb)
+        x, y, r, _ = orc.solve(qp, s, x0=None if x0s is None else x0s[i],
+                               y0=None if y0s is None else y0s[i])
+        out.append((x, y, r, nA, nQ))
+    return out
+
+
+def _compare(batch, xg, yg, rg, ref):
+    for i, (xo, yo, ro, _, _) in enumerate(ref):
+        v0, v1 = batch.var_off[i], batch.var_off[i + 1]
+        r0, r1 = batch.row_off[i], batch.row_off[i + 1]
+        g = rg[i]
+        print(f"  [{i}] {batch.names[i]}: oracle it={ro['iterations']} rel={ro['rel_kkt']:.3e} | "
+              f"gpu it={g['iterations']} rel={g['rel_kkt']:.3e}", flush=True)
+        assert g["status"] == ro["status"]
+        assert g["iterations"] == ro["iterations"]
+        assert g["restarts"] == ro["restarts"]
+        assert g["used_warm_start"] == ro["used_warm_start"]
+        assert abs(g["rel_kkt"] - ro["rel_kkt"]) <= 1e-8
+        assert abs(g["primal_obj"] - ro["primal_obj"]) <= 1e-8 * (1 + abs(ro["primal_obj"]))
+        zo = np.concatenate([xo, yo])
+        zg = np.concatenate([xg[v0:v1], yg[r0:r1]])
+        assert np.max(np.abs(zg - zo)) <= 1e-8 * (1 + np.max(np.abs(zo)))
+
+
+def test_batch_matches_oracle_per_instance(orc, qpa):
+    insts = _mixed_batch()
+    batch = qpgen.concat_batch(insts)
+    ref = _oracle_all(orc, insts, eps=1e-6)
+    with_norms = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6))
+    with_norms.set_norms([r[3] for r in ref], [r[4] for r in ref])
+    xg, yg, rg = with_norms.solve()
+    with_norms.close()
+    _compare(batch, xg, yg, rg, ref)
+
+
+def test_batch_power_iteration_norms(orc, qpa):
+    insts = _mixed_batch()
+    batch = qpgen.concat_batch(insts)
+    bs = qpa.BatchSolver(batch, qpa.Settings())
+    gA, gQ = bs.norms()
+    bs.close()
+    for i, qp in enumerate(insts):
+        nA, _ = orc.norm_A(qp, 1000, 1e-7)
+        nQ, _ = orc.norm_Q(qp, 1000, 1e-7)
+        assert gA[i] == pytest.approx(nA, rel=1e-5, abs=1e-12)
+        assert gQ[i] == pytest.approx(nQ, rel=1e-5)
+
+
+def test_batch_team_sizes_agree(orc, qpa):
+    """Every team size gives the same iterates (row sums are per thread in CSR order);
+    the autotuner returns valid team sizes."""
+    insts = _mixed_batch()[:8]
+    batch = qpgen.concat_batch(insts)
+    ref = _oracle_all(orc, insts, eps=1e-6)
+    bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6))
+    bs.set_norms([r[3] for r in ref], [r[4] for r in ref])
+    for t in (64, 128, 256, 512):
+        bs.set_threads([t] * 4)
+        xg, yg, rg = bs.solve()
+        _compare(batch, xg, yg, rg, ref)
+    chosen = bs.autotune(sample=8, iters=64)
+    assert all(c in (64, 128, 256, 512) for c in chosen)
+    xg, yg, rg = bs.solve()
+    _compare(batch, xg, yg, rg, ref)
+    bs.close()
+
+
+def test_batch_warm_starts_and_limits(orc, qpa):
+    insts = _mixed_batch()[:6]
+    batch = qpgen.concat_batch(insts)
+    sols = _oracle_all(orc, insts, eps=1e-9)
+    rng = np.random.default_rng(1)
+    x0s = [s[0] + 1e-3 * rng.standard_normal(s[0].size) for s in sols]
+    y0s = [s[1] + 1e-3 * rng.standard_normal(s[1].size) for s in sols]
+    x0s[2] = np.full_like(x0s[2], 1e6)       # rejected by the fallback test
+    ref = _oracle_all(orc, insts, eps=1e-6, x0s=x0s, y0s=y0s)
+    bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6))
+    bs.set_norms([r[3] for r in ref], [r[4] for r in ref])
+    xg, yg, rg = bs.solve(x0=np.concatenate(x0s), y0=np.concatenate(y0s))
+    _compare(batch, xg, yg, rg, ref)
+    assert rg[2]["used_warm_start"] == 0 and rg[0]["used_warm_start"] == 1
+    bs.close()
+    # iteration limit not a multiple of the evaluation interval
+    ref2 = _oracle_all(orc, insts, eps=0.0, max_iter=150)
+    bs = qpa.BatchSolver(batch, qpa.Settings(eps=0.0, max_iter=150))
+    bs.set_norms([r[3] for r in ref2], [r[4] for r in ref2])
+    xg, yg, rg = bs.solve()
+    _compare(batch, xg, yg, rg, ref2)
+    assert all(r["iterations"] == 150 and r["status"] == 1 for r in rg)
+    bs.close()
+
+
+def test_batch_equals_single_solves(qpa):
+    insts = _mixed_batch()[:5]
+    batch = qpgen.concat_batch(insts)
+    bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6))
+    gA, gQ = bs.norms()
+    xg, yg, rg = bs.solve()
+    bs.close()
+    for i, qp in enumerate(insts):
+        with qpa.Solver(qp, qpa.Settings(eps=1e-6, norm_A=gA[i], norm_Q=gQ[i])) as s:
+            x, y, r = s.solve()
+        assert r["iterations"] == rg[i]["iterations"]
+        np.testing.assert_allclose(x, xg[batch.var_off[i]:batch.var_off[i + 1]], rtol=1e-9,
+                                   atol=1e-9)
