@@ -47,6 +47,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--graph", action="store_true",
                     help="time with graph replay instead of per-kernel hipEvents")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched MPC section")
+    ap.add_argument("--no-warmstart", action="store_true",
+                    help="skip the learned warm-start section")
+    ap.add_argument("--ws-count", type=int, default=20000,
+                    help="portfolio-family instances for the warm-start section")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
@@ -171,7 +176,97 @@ def main():
         log(f"[bench] cpu oracle {ro['iterations'] / dt:.2f} iters/s ({dt:.1f}s)")
 
     solver.close()
+    if not args.no_batch:
+        out["batched_mpc"] = bench_batch(log)
+    if not args.no_warmstart:
+        out["warm_start"] = bench_warmstart(log, args.ws_count)
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(log):
+    """4096 MPC-style QPs (uneven sizes) to relKKT 1e-6 in one persistent launch per size
+    class, against looping single-instance solves over a sample."""
+    import numpy as np
+    import paper_2311_07710_amd as qpa
+    import qpgen
+    t = time.time()
+    batch = qpgen.mpc_batch(seed=4, count=4096)
+    log(f"[bench] MPC batch generated in {time.time() - t:.1f}s "
+        f"(sum n={batch.var_off[-1]}, sum m={batch.row_off[-1]})")
+    t = time.time()
+    bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6))
+    create_s = time.time() - t
+    t = time.perf_counter()
+    threads = bs.autotune(sample=128, iters=256)
+    tune_s = time.perf_counter() - t
+    t = time.perf_counter()
+    _, _, res = bs.solve()
+    dt = time.perf_counter() - t
+    its = np.array([r["iterations"] for r in res])
+    ok = int(sum(r["status"] == 0 for r in res))
+    gA, gQ = bs.norms()
+    bs.close()
+    log(f"[bench] batched: {batch.count} instances in {dt:.3f}s ({batch.count / dt:.0f}/s), "
+        f"{ok} optimal, threads {threads}")
+    sample = list(range(0, batch.count, 256))
+    t = time.perf_counter()
+    single_its = 0
+    for i in sample:
+        with qpa.Solver(batch.instance(i), qpa.Settings(eps=1e-6, norm_A=gA[i],
+                                                         norm_Q=gQ[i])) as s:
+            _, _, r = s.solve()
+            single_its += r["iterations"]
+    st = time.perf_counter() - t
+    log(f"[bench] looping qp_solve over {len(sample)} instances: {st:.2f}s "
+        f"({len(sample) / st:.1f}/s)")
+    return {"workload": "4096 MPC QPs, T~U{10..100}, n_x~U{4..12}, n_u~U{2..4}, FP64, eps 1e-6",
+            "instances_per_s": batch.count / dt, "seconds": dt, "optimal": ok,
+            "iterations_mean": float(its.mean()), "iterations_max": int(its.max()),
+            "threads_per_class": threads, "autotune_s": tune_s, "create_s": create_s,
+            "single_loop_instances_per_s": len(sample) / st, "single_loop_sample": len(sample),
+            "speedup_vs_single_loop": (batch.count / dt) / (len(sample) / st)}
+
+
+def bench_warmstart(log, count):
+    """Learned warm start on the portfolio family (n_assets 5000, k 100): labels from
+    batched cold solves at 1e-8, MLP 10001-512-512-5202 trained by the library's BF16
+    kernels on 80 %, warm vs cold to relKKT 1e-6 on the held-out 20 %."""
+    import numpy as np
+    import paper_2311_07710_amd as qpa
+    from paper_2311_07710_amd import warmstart as ws
+    import qpgen
+    t = time.time()
+    fam = qpgen.portfolio_family(seed=5, count=count)
+    ntr = int(0.8 * count)
+    tr, te = np.arange(ntr), np.arange(ntr, count)
+    log(f"[bench] portfolio family generated in {time.time() - t:.1f}s")
+    X, Y, res, t_lab = ws.solve_family(fam, tr, qpa.Settings(eps=1e-8))
+    omega = np.array([r["omega"] for r in res])
+    log(f"[bench] {ntr} label solves (1e-8) in {t_lab:.1f}s")
+    t = time.perf_counter()
+    model = ws.train(ws.features(fam, tr), ws.targets(X, Y, omega), fam.base.n, fam.base.m,
+                     hidden=(512, 512), epochs=30, batch=256, lr=1e-3, seed=0)
+    train_s = time.perf_counter() - t
+    log(f"[bench] MLP trained in {train_s:.1f}s, loss {model.history[0]:.4f} -> "
+        f"{model.history[-1]:.4f}")
+    t = time.perf_counter()
+    x0, y0, w0 = model.predict(ws.features(fam, te))
+    pred_s = time.perf_counter() - t
+    _, _, cold, t_cold = ws.solve_family(fam, te, qpa.Settings(eps=1e-6))
+    _, _, warm, t_warm = ws.solve_family(fam, te, qpa.Settings(eps=1e-6), x0=x0, y0=y0, omega0=w0)
+    ci = np.array([r["iterations"] for r in cold], dtype=float)
+    wi = np.array([r["iterations"] for r in warm], dtype=float)
+    kept = int(sum(r["used_warm_start"] for r in warm))
+    okw = int(sum(r["status"] == 0 for r in warm))
+    log(f"[bench] held-out {te.size}: cold {ci.mean():.0f} it / {t_cold:.2f}s, warm "
+        f"{wi.mean():.0f} it / {t_warm:.2f}s (+{pred_s:.2f}s inference), kept {kept}")
+    return {"workload": f"portfolio family n_assets=5000 k=100, {count} instances "
+                        f"({ntr} train / {te.size} held out), eps 1e-6",
+            "cold_iterations_mean": ci.mean(), "warm_iterations_mean": wi.mean(),
+            "cold_seconds": t_cold, "warm_seconds": t_warm, "inference_seconds": pred_s,
+            "warm_kept": kept, "warm_optimal": okw, "held_out": int(te.size),
+            "label_solve_seconds": t_lab, "train_seconds": train_s,
+            "loss_first_epoch": model.history[0], "loss_last_epoch": model.history[-1]}
 
 
 if __name__ == "__main__":

@@ -83,7 +83,7 @@ SIGNATURES = {
     "qp_get_check_log": (C.c_int, [_vp, C.POINTER(qp_check_info), C.c_int64,
                                    C.POINTER(C.c_int64)]),
     "qp_get_profile": (C.c_int, [_vp, C.POINTER(qp_profile)]),
-    "qp_get_norms": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "qp_get_norms": (C.c_int, [_vp, _vp, _vp]),
     "qp_update_vectors": (C.c_int, [_vp, _vp, _vp]),
     "qp_set_norms": (C.c_int, [_vp, _vp, _vp]),
     "qp_batch_autotune": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp]),
@@ -91,6 +91,19 @@ SIGNATURES = {
     "qp_free": (None, [_vp]),
     "qp_last_error": (C.c_char_p, []),
     "qp_version": (C.c_int, []),
+}
+
+# every function declared in include/qp_mlp.h
+MLP_SIGNATURES = {
+    "qp_mlp_create": (C.c_int, [C.c_int32, _vp, C.c_int32, C.c_int32, C.POINTER(_vp)]),
+    "qp_mlp_free": (None, [_vp]),
+    "qp_mlp_num_params": (C.c_int64, [_vp]),
+    "qp_mlp_set_params": (C.c_int, [_vp, _vp]),
+    "qp_mlp_get_params": (C.c_int, [_vp, _vp]),
+    "qp_mlp_get_grads": (C.c_int, [_vp, _vp]),
+    "qp_mlp_forward": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
+    "qp_mlp_backward": (C.c_int, [_vp, _vp, C.c_int32, C.POINTER(C.c_float)]),
+    "qp_mlp_adam_step": (C.c_int, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32]),
 }
 
 _lib = None
@@ -104,7 +117,7 @@ def load():
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -c 'import __graft_entry__ as g; g.build()'`")
         lib = C.CDLL(LIB_PATH)
-        for name, (res, args) in SIGNATURES.items():
+        for name, (res, args) in {**SIGNATURES, **MLP_SIGNATURES}.items():
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args

@@ -137,6 +137,167 @@ struct DevPartition {
     }
 };
 
+struct HostPanels {
+    int np = 1;
+    std::vector<PBlock> blk;
+    std::vector<int32_t> map, rowptr, col, lr_first, lr_nchunk;
+    std::vector<double> val;
+    int grid = 0;
+};
+
+// Splits the columns of an R x C CSR matrix into np ranges of equal nonzero
+// count and builds one CSR per range plus row blocks pinned to XCD groups.
+HostPanels build_panels(const int32_t *rowptr, const int32_t *col, const double *val, int64_t R,
+                        int64_t C, int np) {
+    HostPanels hp;
+    hp.np = np;
+    const int64_t nnz = rowptr[R];
+    std::vector<int64_t> cum(C + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) cum[col[e] + 1]++;
+    for (int64_t c = 0; c < C; ++c) cum[c + 1] += cum[c];
+    std::vector<int64_t> bound(np + 1, C);
+    bound[0] = 0;
+    for (int k = 1; k < np; ++k) {
+        const int64_t target = (nnz * k + np - 1) / np;
+        bound[k] = std::lower_bound(cum.begin(), cum.end(), target) - cum.begin();
+        if (bound[k] < bound[k - 1]) bound[k] = bound[k - 1];
+        if (bound[k] > C) bound[k] = C;
+    }
+    std::vector<int32_t> pcol(C);
+    for (int k = 0; k < np; ++k)
+        for (int64_t c = bound[k]; c < bound[k + 1]; ++c) pcol[c] = k;
+    // per-panel row counts -> global row pointers
+    hp.rowptr.assign((size_t)np * (R + 1), 0);
+    std::vector<int64_t> base(np + 1, 0);
+    {
+        std::vector<int64_t> cnt((size_t)np * R, 0);
+        for (int64_t r = 0; r < R; ++r)
+            for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) cnt[(size_t)pcol[col[e]] * R + r]++;
+        int64_t pos = 0;
+        for (int k = 0; k < np; ++k) {
+            base[k] = pos;
+            for (int64_t r = 0; r < R; ++r) {
+                hp.rowptr[(size_t)k * (R + 1) + r] = (int32_t)pos;
+                pos += cnt[(size_t)k * R + r];
+            }
+            hp.rowptr[(size_t)k * (R + 1) + R] = (int32_t)pos;
+        }
+        base[np] = pos;
+    }
+    hp.col.resize(nnz);
+    hp.val.resize(nnz);
+    {
+        std::vector<int64_t> next((size_t)np * R);
+        for (int k = 0; k < np; ++k)
+            for (int64_t r = 0; r < R; ++r) next[(size_t)k * R + r] = hp.rowptr[(size_t)k * (R + 1) + r];
+        for (int64_t r = 0; r < R; ++r)
+            for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+                const int k = pcol[col[e]];
+                const int64_t q = next[(size_t)k * R + r]++;
+                hp.col[q] = col[e];
+                hp.val[q] = val[e];
+            }
+    }
+    // row blocks of each panel
+    std::vector<std::vector<int32_t>> per_panel(np);
+    for (int k = 0; k < np; ++k) {
+        const int32_t *rp = hp.rowptr.data() + (size_t)k * (R + 1);
+        int64_t r = 0;
+        while (r < R) {
+            const int64_t len = (int64_t)rp[r + 1] - rp[r];
+            if (len > NNZ_BLK) {
+                const int32_t nch = (int32_t)((len + NNZ_BLK - 1) / NNZ_BLK);
+                const int32_t id = (int32_t)hp.lr_first.size();
+                hp.lr_first.push_back((int32_t)hp.blk.size());
+                hp.lr_nchunk.push_back(nch);
+                for (int32_t ch = 0; ch < nch; ++ch) {
+                    PBlock b{};
+                    b.row0 = (int32_t)r;
+                    b.row1 = (int32_t)r + 1;
+                    b.e0 = rp[r] + ch * NNZ_BLK;
+                    b.e1 = (int32_t)std::min<int64_t>((int64_t)b.e0 + NNZ_BLK, rp[r + 1]);
+                    b.panel = k;
+                    b.lr = id;
+                    per_panel[k].push_back((int32_t)hp.blk.size());
+                    hp.blk.push_back(b);
+                }
+                ++r;
+            } else {
+                const int64_t r0 = r, e0 = rp[r];
+                while (r < R && r - r0 < PANEL_ROWS && (int64_t)rp[r + 1] - e0 <= NNZ_BLK) ++r;
+                PBlock b{};
+                b.row0 = (int32_t)r0;
+                b.row1 = (int32_t)r;
+                b.e0 = (int32_t)e0;
+                b.e1 = rp[r];
+                b.panel = k;
+                b.lr = -1;
+                per_panel[k].push_back((int32_t)hp.blk.size());
+                hp.blk.push_back(b);
+            }
+        }
+    }
+    // workgroup w runs on XCD w % 8: XCD x serves panel x / (8/np), every (8/np)-th block
+    const int s = 8 / np;
+    std::vector<std::vector<int32_t>> lists(8);
+    for (int x = 0; x < 8; ++x) {
+        const int k = x / s, xo = x % s;
+        for (size_t b = 0; b < per_panel[k].size(); ++b)
+            if ((int)(b % s) == xo) lists[x].push_back(per_panel[k][b]);
+    }
+    size_t maxlen = 0;
+    for (auto &l : lists) maxlen = std::max(maxlen, l.size());
+    hp.grid = (int)(8 * maxlen);
+    hp.map.assign(hp.grid, -1);
+    for (int x = 0; x < 8; ++x)
+        for (size_t l = 0; l < lists[x].size(); ++l) hp.map[l * 8 + x] = lists[x][l];
+    return hp;
+}
+
+struct DevPanels {
+    DevMem blk, map, rowptr, col, val, lr_first, lr_nchunk, lr_count, lr_partial, part;
+    Panels view{};
+    int upload(const HostPanels &hp, int64_t R) {
+        int rc;
+        if ((rc = blk.upload(hp.blk.data(), hp.blk.size() * sizeof(PBlock))) ||
+            (rc = map.upload(hp.map.data(), hp.map.size() * 4)) ||
+            (rc = rowptr.upload(hp.rowptr.data(), hp.rowptr.size() * 4)) ||
+            (rc = col.upload(hp.col.data(), hp.col.size() * 4)) ||
+            (rc = val.upload(hp.val.data(), hp.val.size() * 8)) ||
+            (rc = lr_first.upload(hp.lr_first.data(), hp.lr_first.size() * 4)) ||
+            (rc = lr_nchunk.upload(hp.lr_nchunk.data(), hp.lr_nchunk.size() * 4)) ||
+            (rc = lr_count.alloc(std::max<size_t>(hp.lr_first.size(), 1) * 4)) ||
+            (rc = lr_partial.alloc(std::max<size_t>(hp.blk.size(), 1) * 4 * 8)) ||
+            (rc = part.alloc(std::max<size_t>((size_t)hp.np * R, 1) * 8)))
+            return rc;
+        HIPCHK(hipMemset(lr_count.p, 0, lr_count.bytes));
+        view.blk = blk.as<PBlock>();
+        view.map = map.as<int32_t>();
+        view.rowptr = rowptr.as<int32_t>();
+        view.col = col.as<int32_t>();
+        view.val = val.as<double>();
+        view.lr_first = lr_first.as<int32_t>();
+        view.lr_nchunk = lr_nchunk.as<int32_t>();
+        view.lr_count = lr_count.as<int32_t>();
+        view.lr_partial = lr_partial.as<double>();
+        view.part = part.as<double>();
+        view.np = hp.np;
+        view.nblk = (int32_t)hp.blk.size();
+        view.grid = hp.grid;
+        view.nlr = (int32_t)hp.lr_first.size();
+        view.R = R;
+        return QP_OK;
+    }
+};
+
+// panel count: explicit setting, else 4 (two XCDs per panel) when the gathered
+// vector exceeds 2 MB, i.e. would not stay in one XCD's 4 MB L2 next to the
+// streamed matrix (4 measured fastest among 1/2/4/8 on the large random QP)
+int choose_panels(int32_t setting, int64_t gathered_len) {
+    if (setting == 1 || setting == 2 || setting == 4 || setting == 8) return setting;
+    return gathered_len * 8 > (2 << 20) ? 4 : 1;
+}
+
 // copies `count` elements of an input array (host or device) to a host vector
 template <class T>
 int fetch(std::vector<T> &dst, const T *src, int64_t count, int mem_space) {
@@ -183,6 +344,8 @@ struct qp_handle {
     DevMem a_rowptr, a_col, a_val, p_rowptr, p_col, p_val;
     DevMem c, b, l, u, rt;
     DevPartition partA, partP;
+    DevPanels panA, panP;    // column-panel layouts of A and P (np > 1)
+    int npA = 1, npP = 1;
     Csr A{}, P{};
     double norm_A = 0.0, norm_Q = 0.0, c_inf = 0.0, b_inf = 0.0, c_norm2 = 0.0, b_norm2 = 0.0;
     double dual_bytes = 0.0, primal_bytes = 0.0;  // algorithmic HBM bytes of one launch
@@ -489,6 +652,16 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
                           72.0 * (double)n;
     }
     if ((rc = h->partA.upload(hpA)) || (rc = h->partP.upload(hpP))) return rc;
+    h->npA = m > 0 ? choose_panels(h->set.panels_dual, n) : 1;
+    h->npP = choose_panels(h->set.panels_primal, n + m);
+    if (h->npA > 1) {
+        HostPanels pa = build_panels(ar.data(), ac.data(), av.data(), m, n, h->npA);
+        if ((rc = h->panA.upload(pa, m))) return rc;
+    }
+    if (h->npP > 1) {
+        HostPanels pp = build_panels(pr.data(), pc.data(), pv.data(), n, n + m, h->npP);
+        if ((rc = h->panP.upload(pp, n))) return rc;
+    }
     set_vectors_host_stats(h, c, b);
 
     // solver vectors
@@ -552,9 +725,11 @@ void enqueue_interval(qp_handle *h, const DevSettings &ds, int md_in, int len, b
     int md = md_in;
     for (int j = 0; j < len; ++j) {
         if (timed) (void)hipEventRecord(h->prof_ev[4 * j + 0], s);
-        launch_dual(s, h->partA.view, h->A, h->vecs, tab + j, st);
+        if (h->npA > 1) launch_dual_panels(s, h->panA.view, h->vecs, h->n, tab + j, st);
+        else launch_dual(s, h->partA.view, h->A, h->vecs, tab + j, st);
         if (timed) (void)hipEventRecord(h->prof_ev[4 * j + 1], s);
-        launch_primal(s, h->partP.view, h->P, h->vecs, md, tab + j, st, h->n);
+        if (h->npP > 1) launch_primal_panels(s, h->panP.view, h->vecs, md, h->n, tab + j, st);
+        else launch_primal(s, h->partP.view, h->P, h->vecs, md, tab + j, st, h->n);
         if (timed) (void)hipEventRecord(h->prof_ev[4 * j + 2], s);
         md ^= 1;
     }

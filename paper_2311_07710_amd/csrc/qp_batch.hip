@@ -61,6 +61,7 @@ struct BatchDev {
     const int64_t *clock0;
     int64_t deadline_ticks;  // 0: no time limit
     int32_t warm_fallback, any_warm;
+    int32_t lds_doubles;     // dynamic LDS per team (doubles); 0: gathered vectors in HBM
 };
 
 // ---------------------------------------------------------------------------
@@ -187,6 +188,7 @@ __device__ __forceinline__ double proj_box_b(double v, double lo, double hi) {
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
+    extern __shared__ double smem[];  // x~ | x_md[0] | x_md[1] | y when they fit
     __shared__ int s_q;
     __shared__ State S;
     __shared__ Step stp[2];
@@ -205,9 +207,14 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
         const int32_t *prp = a.p_rowptr + v0;
         const double *c = a.c + v0, *l = a.l + v0, *u = a.u + v0, *b = a.b + r0;
         const uint8_t *rt = a.rt + r0;
-        double *x = a.x + v0, *xbar = a.xbar + v0, *xt = a.xt + v0, *xrs = a.xrs + v0;
-        double *xmd[2] = {a.xmd0 + v0, a.xmd1 + v0};
-        double *y = a.y + r0, *ybar = a.ybar + r0, *yrs = a.yrs + r0;
+        double *x = a.x + v0, *xbar = a.xbar + v0, *xrs = a.xrs + v0;
+        double *ybar = a.ybar + r0, *yrs = a.yrs + r0;
+        // the gathered vectors (x~ in the dual phase, x_md and y in the primal
+        // phase) live in LDS when the instance fits, else in HBM
+        const bool in_lds = 3 * n + m <= a.lds_doubles;
+        double *xt = in_lds ? smem : a.xt + v0;
+        double *xmd[2] = {in_lds ? smem + n : a.xmd0 + v0, in_lds ? smem + 2 * n : a.xmd1 + v0};
+        double *y = in_lds ? smem + 3 * n : a.y + r0;
         DevSettings ds = base;
         ds.norm_A = a.normA[id];
         ds.norm_Q = a.normQ[id];
@@ -486,6 +493,8 @@ struct BatchData {
     std::vector<uint8_t> h_hx, h_hy;
     int wall_khz = 100000;
     int num_cu = 256;
+    int use_lds = 1;
+    int32_t lds_need[NCLASS] = {0, 0, 0, 0};  // doubles of dynamic LDS per class
 };
 
 static int class_of(int64_t rows) {
@@ -538,9 +547,9 @@ static BatchDev make_dev(BatchData *bd) {
 }
 
 template <class K>
-static int persistent_grid(K kernel, int nt, int count, int num_cu) {
+static int persistent_grid(K kernel, int nt, int count, int num_cu, size_t lds = 0) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     int g = per_cu * num_cu;
@@ -563,8 +572,9 @@ static void launch_class(BatchData *bd, BatchDev a, const DevSettings &ds, int n
             hipLaunchKernelGGL(k_batch_norms<NT>, dim3(g), dim3(NT), 0, s, a, maxit, rtol,       \
                                bd->normA_d.as<double>(), bd->normQ_d.as<double>());              \
         } else {                                                                                 \
-            int g = persistent_grid(k_batch<NT>, NT, a.order_count, bd->num_cu);                 \
-            hipLaunchKernelGGL(k_batch<NT>, dim3(g), dim3(NT), 0, s, a, ds);                     \
+            const size_t lds = (size_t)a.lds_doubles * 8;                                        \
+            int g = persistent_grid(k_batch<NT>, NT, a.order_count, bd->num_cu, lds);            \
+            hipLaunchKernelGGL(k_batch<NT>, dim3(g), dim3(NT), lds, s, a, ds);                   \
         }                                                                                        \
     } while (0)
     switch (nt) {
@@ -797,6 +807,22 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
     }
     int dev = 0;
     (void)hipGetDevice(&dev);
+    {
+        // dynamic LDS per class: the largest 3 n_i + m_i that fits the cap
+        int max_lds = 65536;
+        (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        const int cap = std::min(max_lds, 64 * 1024) - 4096;  // room for the static LDS
+        for (int k = 0; k < NCLASS; ++k) {
+            int64_t need = 0;
+            for (int32_t id : bd->order[k]) {
+                const int64_t nv = bd->var_off[id + 1] - bd->var_off[id];
+                const int64_t mv = bd->row_off[id + 1] - bd->row_off[id];
+                const int64_t w = 3 * nv + mv;
+                if (w * 8 <= cap) need = std::max(need, w);
+            }
+            bd->lds_need[k] = (int32_t)need;
+        }
+    }
     (void)hipDeviceGetAttribute(&bd->wall_khz, hipDeviceAttributeWallClockRate, dev);
     (void)hipDeviceGetAttribute(&bd->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (bd->wall_khz <= 0) bd->wall_khz = 100000;
@@ -930,6 +956,7 @@ static int run_batch(BatchData *bd, const qp_settings *s, int ms, const qp_warm_
     for (int k = 0; k < NCLASS; ++k) {
         int lo = bd->order_off[k], hi = bd->order_off[k + 1];
         if (max_count && max_count[k] >= 0 && hi - lo > max_count[k]) hi = lo + max_count[k];
+        a.lds_doubles = bd->use_lds ? bd->lds_need[k] : 0;
         launch_class(bd, a, ds, threads[k], lo, hi, false, 0, 0.0);
     }
     HIPCHK(hipGetLastError());

@@ -31,6 +31,38 @@ struct Blocks {
     int32_t nblk, nlr;
 };
 
+// Column-panel layout of a matrix for the hot phases.  The columns are split
+// into `np` ranges of equal nonzero count; panel k holds the entries of every
+// row whose column falls in range k (original order within a row), as its own
+// CSR (row pointers are global positions into col/val).  Panel k's row blocks
+// run only on the XCDs k*(8/np) .. (k+1)*(8/np)-1 (workgroup w runs on XCD
+// w % 8), so the slice of the gathered vector a panel touches stays in those
+// XCDs' L2.  Each block writes one partial sum per row to part[k][row]; a
+// combine kernel adds the np partials in panel order and runs the epilogue.
+struct PBlock {
+    int32_t row0, row1;  // rows [row0, row1)
+    int32_t e0, e1;      // positions [e0, e1) in col/val
+    int32_t panel;
+    int32_t lr;          // long-row id (chunk of a row longer than NNZ_BLK) or -1
+    int32_t pad0, pad1;
+};
+
+struct Panels {
+    const PBlock *blk;
+    const int32_t *map;       // [grid] block of workgroup w, -1 = idle slot
+    const int32_t *rowptr;    // [np * (R + 1)]
+    const int32_t *col;
+    const double *val;
+    const int32_t *lr_first, *lr_nchunk;
+    int32_t *lr_count;
+    double *lr_partial;       // [nblk * 4]
+    double *part;             // [np * R]
+    int32_t np, nblk, grid, nlr;
+    int64_t R;
+};
+
+constexpr int PANEL_ROWS = 1024;  // rows per panel block
+
 struct Csr {
     const int32_t *rowptr;
     const int32_t *col;
@@ -104,6 +136,12 @@ void launch_init(hipStream_t s, const Vecs &v, const double *x0, const double *y
                  int64_t m, int pair_with_cold);
 void launch_fallback_apply(hipStream_t s, const Vecs &v, const State *st, int64_t n, int64_t m);
 void launch_state_reset(hipStream_t s, State *st, double omega, int64_t max_iter);
+
+// column-panel phases (partials + combine)
+void launch_dual_panels(hipStream_t s, const Panels &pn, const Vecs &v, int64_t n,
+                        const Step *step, const State *st);
+void launch_primal_panels(hipStream_t s, const Panels &pn, const Vecs &v, int md_in, int64_t n,
+                          const Step *step, const State *st);
 
 // power iteration helpers: y = M_1 x + sign2 * M_2 x2 where M_1 holds the
 // entries with col < split and M_2 those with col >= split (x or x2 may be null)

@@ -810,3 +810,154 @@ void launch_fill(hipStream_t s, double *dst, int64_t n, double value) {
 }
 
 }  // namespace qpk
+
+// ---------------------------------------------------------------------------
+// column-panel phases: per-panel partial row sums, then a combine + epilogue
+// ---------------------------------------------------------------------------
+namespace qpk {
+
+// chunk partials of a long row in a panel (same protocol as chunk_finish)
+__device__ bool panel_chunk_finish(const Panels &pn, int bi, int lr, double part, double *tot) {
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+        pn.lr_partial[(size_t)bi * 4] = part;
+        __threadfence();
+        const int old = atomicAdd(&pn.lr_count[lr], 1);
+        is_last = (old == pn.lr_nchunk[lr] - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int f = pn.lr_first[lr], nc = pn.lr_nchunk[lr];
+        double t = 0.0;
+        for (int ch = 0; ch < nc; ++ch)
+            t = t + __hip_atomic_load(&pn.lr_partial[(size_t)(f + ch) * 4], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+        *tot = t;
+        __hip_atomic_store(&pn.lr_count[lr], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return threadIdx.x == 0;
+}
+
+// PHASE only distinguishes the dual and primal instances in profiles.
+// Gathers v1[c] for c < split and v2[c - split] otherwise.
+template <int PHASE>
+__global__ __launch_bounds__(BS) void k_panel_spmv(Panels pn, const double *__restrict__ v1,
+                                                   const double *__restrict__ v2, int32_t split,
+                                                   const State *__restrict__ st) {
+    if (st->done) return;
+    const int bi = pn.map[blockIdx.x];
+    if (bi < 0) return;
+    __shared__ double prod[NNZ_BLK];
+    __shared__ double scratch[BS / 64];
+    const PBlock B = pn.blk[bi];
+    const int t = threadIdx.x;
+    int cols[EPT];
+    double vals[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = B.e0 + i * BS + t;
+        if (e < B.e1) {
+            cols[i] = __builtin_nontemporal_load(&pn.col[e]);
+            vals[i] = __builtin_nontemporal_load(&pn.val[e]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = B.e0 + i * BS + t;
+        if (e < B.e1) {
+            const int cc = cols[i];
+            const double v = cc < split ? v1[cc] : v2[cc - split];
+            prod[i * BS + t] = vals[i] * v;
+        }
+    }
+    __syncthreads();
+    const int32_t *rp = pn.rowptr + (size_t)B.panel * (size_t)(pn.R + 1);
+    double *out = pn.part + (size_t)B.panel * (size_t)pn.R;
+    if (B.lr < 0) {
+        const int nrows = B.row1 - B.row0;
+        if (nrows >= BS) {
+            for (int rl = t; rl < nrows; rl += BS) {
+                const int row = B.row0 + rl;
+                const int e1 = rp[row + 1] - B.e0;
+                double s = 0.0;
+                for (int e = rp[row] - B.e0; e < e1; ++e) s = s + prod[e];
+                out[row] = s;
+            }
+        } else {
+            const int G = lanes_per_row(nrows);
+            const int rl = t / G, lane = t % G;
+            double s = 0.0;
+            if (rl < nrows) {
+                const int row = B.row0 + rl;
+                const int e1 = rp[row + 1] - B.e0;
+                for (int e = rp[row] - B.e0 + lane; e < e1; e += G) s = s + prod[e];
+            }
+            s = group_sum(s, G);
+            if (rl < nrows && lane == 0) out[B.row0 + rl] = s;
+        }
+    } else {
+        const double part = block_sum_lds(prod, B.e1 - B.e0, scratch);
+        double tot;
+        if (panel_chunk_finish(pn, bi, B.lr, part, &tot)) out[B.row0] = tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dual_combine(const double *__restrict__ part, int32_t np,
+                                                      int64_t m, double *__restrict__ y,
+                                                      double *__restrict__ ybar,
+                                                      const double *__restrict__ b,
+                                                      const uint8_t *__restrict__ rt,
+                                                      const Step *__restrict__ step,
+                                                      const State *__restrict__ st) {
+    if (st->done) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double s = part[i];
+    for (int k = 1; k < np; ++k) s = s + part[(size_t)k * m + i];
+    dual_epilogue((int)i, s, y, ybar, b, rt, step->d, step->w);
+}
+
+__global__ __launch_bounds__(256) void k_primal_combine(const double *__restrict__ part,
+                                                        int32_t np, int64_t n, PrimalArgs a,
+                                                        const Step *__restrict__ step,
+                                                        const State *__restrict__ st) {
+    if (st->done) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = part[j];
+    for (int k = 1; k < np; ++k) s = s + part[(size_t)k * n + j];
+    primal_epilogue((int)j, s, a, step->p, step->w, step->theta_next, step->w_next);
+}
+
+void launch_dual_panels(hipStream_t s, const Panels &pn, const Vecs &v, int64_t n,
+                        const Step *step, const State *st) {
+    if (pn.R == 0) return;
+    if (pn.grid > 0)
+        hipLaunchKernelGGL(k_panel_spmv<0>, dim3(pn.grid), dim3(BS), 0, s, pn, (const double *)v.xt,
+                           (const double *)nullptr, (int32_t)n, st);
+    hipLaunchKernelGGL(k_dual_combine, dim3((unsigned)((pn.R + 255) / 256)), dim3(256), 0, s,
+                       (const double *)pn.part, pn.np, pn.R, v.y, v.ybar, v.b, v.rt, step, st);
+}
+
+void launch_primal_panels(hipStream_t s, const Panels &pn, const Vecs &v, int md_in, int64_t n,
+                          const Step *step, const State *st) {
+    PrimalArgs a;
+    a.xmd_in = v.xmd[md_in];
+    a.y = v.y;
+    a.x = v.x;
+    a.xbar = v.xbar;
+    a.xt = v.xt;
+    a.xmd_out = v.xmd[md_in ^ 1];
+    a.c = v.c;
+    a.l = v.l;
+    a.u = v.u;
+    if (pn.grid > 0)
+        hipLaunchKernelGGL(k_panel_spmv<1>, dim3(pn.grid), dim3(BS), 0, s, pn,
+                           (const double *)v.xmd[md_in], (const double *)v.y, (int32_t)n, st);
+    hipLaunchKernelGGL(k_primal_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (const double *)pn.part, pn.np, n, a, step, st);
+}
+
+}  // namespace qpk

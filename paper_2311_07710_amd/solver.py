@@ -139,7 +139,7 @@ class Solver:
 
     def norms(self):
         a, q = C.c_double(), C.c_double()
-        B.check(self.lib.qp_get_norms(self.h, C.byref(a), C.byref(q)))
+        B.check(self.lib.qp_get_norms(self.h, C.addressof(a), C.addressof(q)))
         return a.value, q.value
 
     def set_norms(self, norm_A: float, norm_Q: float):

@@ -280,19 +280,27 @@ def mpc_qp(rng, T: int, nx: int, nu: int, name: str = "mpc",
     xb = max(10.0, 2.0 * xmax)
     if xb > state_bound_cap:
         xb = np.inf
-    ix = lambda t, j: t * nx + j  # noqa: E731
-    iu = lambda t, j: (T + 1) * nx + t * nu + j  # noqa: E731
-    rows, cols, vals = [], [], []
-    for j in range(nx):
-        rows.append(j); cols.append(ix(0, j)); vals.append(1.0)
-    for t in range(T):
-        for j in range(nx):
-            r = (t + 1) * nx + j
-            for q in range(nx):
-                rows.append(r); cols.append(ix(t, q)); vals.append(-At[t, j, q])
-            rows.append(r); cols.append(ix(t + 1, j)); vals.append(1.0)
-            for q in range(nu):
-                rows.append(r); cols.append(iu(t, q)); vals.append(-Bt[t, j, q])
+    # rows 0..nx-1: x_0 = x_init ; row (t+1)*nx + j: x_{t+1,j} - A_t[j,:] x_t - B_t[j,:] u_t = 0
+    t_idx = np.arange(T)[:, None, None]
+    j_idx = np.arange(nx)[None, :, None]
+    r_dyn = (t_idx + 1) * nx + j_idx                                   # (T, nx, 1)
+    qx = np.arange(nx)[None, None, :]
+    qu = np.arange(nu)[None, None, :]
+    rows = np.concatenate([
+        np.arange(nx),
+        np.broadcast_to(r_dyn, (T, nx, nx)).ravel(),
+        r_dyn.ravel(),
+        np.broadcast_to(r_dyn, (T, nx, nu)).ravel()])
+    cols = np.concatenate([
+        np.arange(nx),
+        (t_idx * nx + qx + 0 * j_idx).ravel(),
+        ((t_idx + 1) * nx + j_idx).ravel(),
+        ((T + 1) * nx + t_idx * nu + qu + 0 * j_idx).ravel()])
+    vals = np.concatenate([
+        np.ones(nx),
+        (-At).ravel(),
+        np.ones(T * nx),
+        (-Bt).ravel()])
     A = sp.csr_matrix((vals, (rows, cols)), shape=(m, n))
     Q = sp.diags(np.concatenate([qd, rd]))
     c = np.zeros(n)

@@ -19,8 +19,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "qp.h")
 
 
-def _declared_functions():
-    src = open(HEADER).read()
+def _declared_functions(header=HEADER):
+    src = open(header).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(qp_\w+)\s*\(", src)))
 
@@ -28,10 +28,14 @@ def _declared_functions():
 def test_library_exports_every_declared_symbol():
     lib = qpa.load()
     names = _declared_functions()
-    assert len(names) >= 11
+    assert len(names) >= 14
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(B.SIGNATURES)
+    mlp_names = _declared_functions(os.path.join(ROOT, "include", "qp_mlp.h"))
+    assert set(mlp_names) == set(B.MLP_SIGNATURES)
+    for n in mlp_names:
+        assert hasattr(lib, n), n
     assert lib.qp_version() == 1
 
 

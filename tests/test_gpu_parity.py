@@ -42,7 +42,8 @@ def _norms(orc, qp):
 
 
 def _pair(orc, qpa, qp, *, eps=1e-6, max_iter=200000, check_every=64, mode=0, fixed_K=100,
-          x0=None, y0=None, omega0=0.0, warm_fallback=1, use_graph=1, norms=None, log=True):
+          x0=None, y0=None, omega0=0.0, warm_fallback=1, use_graph=1, norms=None, log=True,
+          panels=(0, 0)):
     nA, nQ = norms if norms is not None else _norms(orc, qp)
     os_ = orc.OracleSettings(eps=eps, max_iter=max_iter, check_every=check_every,
                              restart_mode=mode, fixed_K=fixed_K, norm_A=nA, norm_Q=nQ,
@@ -50,7 +51,8 @@ def _pair(orc, qpa, qp, *, eps=1e-6, max_iter=200000, check_every=64, mode=0, fi
     xo, yo, ro, lo = orc.solve(qp, os_, x0=x0, y0=y0, omega0=omega0, log_cap=100000)
     gs = qpa.Settings(eps=eps, max_iter=max_iter, check_every=check_every, restart_mode=mode,
                       fixed_K=fixed_K, norm_A=nA, norm_Q=nQ, warm_fallback=warm_fallback,
-                      use_graph=use_graph, log_checks=1 if log else 0)
+                      use_graph=use_graph, log_checks=1 if log else 0,
+                      panels_dual=panels[0], panels_primal=panels[1])
     with qpa.Solver(qp, gs) as s:
         xg, yg, rg = s.solve(x0=x0, y0=y0, omega0=omega0)
         lg = s.check_log()
@@ -131,6 +133,29 @@ def test_power_iteration_norms(orc, qpa, maker):
 def test_large_random_scaled_fixed_iterations(orc, qpa):
     qp = qpgen.large_random_qp(seed=2, n=30000, m=15000)
     o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=640)
+    _assert_parity(orc, qp, o, g)
+
+
+@pytest.mark.parametrize("panels", [(2, 2), (4, 8), (8, 4), (8, 8)])
+def test_column_panels_match_oracle(orc, qpa, panels):
+    """XCD-pinned column panels (partial sums + combine) on both phases."""
+    qp = qpgen.large_random_qp(seed=2, n=30000, m=15000)
+    o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=320, panels=panels)
+    _assert_parity(orc, qp, o, g)
+
+
+@pytest.mark.parametrize("panels", [(8, 8), (2, 4)])
+def test_column_panels_long_rows(orc, qpa, panels):
+    """The 20000-nonzero budget row is split across panels and chunks."""
+    qp = qpgen.portfolio_qp(seed=3, n_assets=20000, k=40)
+    o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=256, panels=panels)
+    _assert_parity(orc, qp, o, g)
+
+
+@pytest.mark.parametrize("panels", [(8, 8), (4, 2)])
+def test_column_panels_tiny_to_tolerance(orc, qpa, panels):
+    qp = qpgen.tiny_random_qp(1)
+    o, g = _pair(orc, qpa, qp, eps=1e-6, panels=panels)
     _assert_parity(orc, qp, o, g)
 
 
@@ -261,8 +286,9 @@ def test_row_lengths_around_block_size(orc, qpa):
     qp = qpgen.instances._make("rowlens", sp.diags(q), A, rng.standard_normal(n), b,
                                np.where(rng.random(n) < 0.5, 0.0, -np.inf),
                                np.where(rng.random(n) < 0.3, 2.0, np.inf), rt)
-    o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=300)
-    _assert_parity(orc, qp, o, g)
+    for panels in ((1, 1), (8, 8)):
+        o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=300, panels=panels)
+        _assert_parity(orc, qp, o, g)
 
 
 def test_equality_only_and_singular_q(orc, qpa):
@@ -301,6 +327,15 @@ def test_device_arrays_path(orc, qpa):
 # ---------------------------------------------------------------------------
 def test_large_random_full_size(orc, qpa):
     qp = qpgen.large_random_qp()
+    nA, _ = orc.norm_A(qp, 40, 1e-7)
+    nQ, _ = orc.norm_Q(qp, 40, 1e-7)
+    o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=64, norms=(nA, nQ))
+    _assert_parity(orc, qp, o, g)
+
+
+def test_portfolio_full_size(orc, qpa):
+    """The full factor-model portfolio QP (n = 5e5 + 1000, a 5e5-nonzero budget row)."""
+    qp = qpgen.portfolio_qp()
     nA, _ = orc.norm_A(qp, 40, 1e-7)
     nQ, _ = orc.norm_Q(qp, 40, 1e-7)
     o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=64, norms=(nA, nQ))
