@@ -48,10 +48,15 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="time with graph replay instead of per-kernel hipEvents")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched MPC section")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the Sec. 5 momentum/restart ablation")
     ap.add_argument("--no-warmstart", action="store_true",
                     help="skip the learned warm-start section")
     ap.add_argument("--ws-count", type=int, default=20000,
                     help="portfolio-family instances for the warm-start section")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (a known-size reference "
+                         "for rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
@@ -65,6 +70,14 @@ def main():
     import qpgen
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy: 256 MiB read + 256 MiB written")
+        del src, dst
     t = time.time()
     qp = qpgen.large_random_qp()
     log(f"[bench] generated n={qp.n} m={qp.m} nnzA={qp.a_nnz} nnzQ={qp.q_nnz} "
@@ -164,20 +177,22 @@ def main():
         import oracle
         onA, _ = oracle.norm_A(qp, 40, 1e-7)
         onQ, _ = oracle.norm_Q(qp, 40, 1e-7)
-        n_it = 96
+        n_it = 448
         t = time.perf_counter()
         _, _, ro, _ = oracle.solve(qp, oracle.OracleSettings(eps=0.0, max_iter=n_it, norm_A=onA,
                                                              norm_Q=onQ))
         dt = time.perf_counter() - t
         out["cpu_baseline"] = {"value": ro["iterations"] / dt, "unit": "iters/s", "cores": 1,
                                "kind": "oracle",
-                               "sample": f"{n_it} rAPDHG iterations (3 KKT evaluations) of the "
+                               "sample": f"{n_it} rAPDHG iterations (KKT checked every 64) of the "
                                          "same full-size instance, single-threaded C oracle"}
         log(f"[bench] cpu oracle {ro['iterations'] / dt:.2f} iters/s ({dt:.1f}s)")
 
     solver.close()
     if not args.no_batch:
         out["batched_mpc"] = bench_batch(log)
+    if not args.no_ablation:
+        out["ablation"] = bench_ablation(log)
     if not args.no_warmstart:
         out["warm_start"] = bench_warmstart(log, args.ws_count)
     print(json.dumps(out), flush=True)
@@ -227,6 +242,46 @@ def bench_batch(log):
             "speedup_vs_single_loop": (batch.count / dt) / (len(sample) / st)}
 
 
+def bench_ablation(log):
+    """Sec. 5's comparison of PDHG, accelerated PDHG, restarted PDHG and rAPDHG, as solved
+    counts and shifted geometric means (shift 10, unsolved = 200000 iterations) over a
+    synthetic stand-in for the paper's test set: 128 MPC QPs and 64 tiny random QPs, each
+    method in one batched launch per tolerance."""
+    import math
+    import numpy as np
+    import paper_2311_07710_amd as qpa
+    import qpgen
+    insts = [qpgen.mpc_batch(seed=6, count=128).instance(i) for i in range(128)]
+    insts += [qpgen.tiny_random_qp(seed) for seed in range(1, 65)]
+    batch = qpgen.concat_batch(insts)
+    methods = (("rAPDHG (Sec. 6 adaptive restart)", 1, 0), ("rAPDHG (Sec. 5 halving)", 1, 2),
+               ("accelerated PDHG (no restart)", 1, 3), ("restarted PDHG (Sec. 5 halving)", 0, 2),
+               ("PDHG (no restart)", 0, 3))
+    norms = None
+    out = {"workload": f"{batch.count} QPs: 128 MPC (seed 6) + 64 tiny random (seeds 1-64), "
+                       "iteration limit 200000", "methods": {}}
+    for eps in (1e-3, 1e-6):
+        for name, mom, mode in methods:
+            bs = qpa.BatchSolver(batch, qpa.Settings(eps=eps, momentum=mom, restart_mode=mode,
+                                                     max_iter=200000))
+            if norms is None:
+                norms = bs.norms()
+            else:
+                bs.set_norms(*norms)
+            t = time.perf_counter()
+            _, _, res = bs.solve()
+            dt = time.perf_counter() - t
+            bs.close()
+            its = np.array([r["iterations"] if r["status"] == 0 else 200000 for r in res], float)
+            solved = int(sum(r["status"] == 0 for r in res))
+            sgm = math.exp(np.mean(np.log(its + 10.0))) - 10.0
+            out["methods"].setdefault(name, {})[f"{eps:g}"] = {
+                "solved": solved, "sgm10_iterations": sgm, "seconds": dt}
+            log(f"[bench] ablation eps {eps:g}: {name}: solved {solved}/{batch.count}, "
+                f"SGM10 {sgm:.0f} iterations, {dt:.2f}s")
+    return out
+
+
 def bench_warmstart(log, count):
     """Learned warm start on the portfolio family (n_assets 5000, k 100): labels from
     batched cold solves at 1e-8, MLP 10001-512-512-5202 trained by the library's BF16
@@ -240,20 +295,26 @@ def bench_warmstart(log, count):
     ntr = int(0.8 * count)
     tr, te = np.arange(ntr), np.arange(ntr, count)
     log(f"[bench] portfolio family generated in {time.time() - t:.1f}s")
-    X, Y, res, t_lab = ws.solve_family(fam, tr, qpa.Settings(eps=1e-8))
+    nA, nQ = ws.family_norms(fam)
+    s8 = qpa.Settings(eps=1e-8, norm_A=nA, norm_Q=nQ)
+    s6 = qpa.Settings(eps=1e-6, norm_A=nA, norm_Q=nQ)
+    X, Y, res, t_lab = ws.solve_family(fam, tr, s8, chunk=2048,
+                                       log=lambda msg: log(f"[bench] labels: {msg}"))
     omega = np.array([r["omega"] for r in res])
     log(f"[bench] {ntr} label solves (1e-8) in {t_lab:.1f}s")
     t = time.perf_counter()
     model = ws.train(ws.features(fam, tr), ws.targets(X, Y, omega), fam.base.n, fam.base.m,
-                     hidden=(512, 512), epochs=30, batch=256, lr=1e-3, seed=0)
+                     hidden=(512, 512), epochs=30, batch=256, lr=1e-3, seed=0,
+                     log=lambda msg: log(f"[bench] train: {msg}"))
     train_s = time.perf_counter() - t
     log(f"[bench] MLP trained in {train_s:.1f}s, loss {model.history[0]:.4f} -> "
         f"{model.history[-1]:.4f}")
     t = time.perf_counter()
     x0, y0, w0 = model.predict(ws.features(fam, te))
     pred_s = time.perf_counter() - t
-    _, _, cold, t_cold = ws.solve_family(fam, te, qpa.Settings(eps=1e-6))
-    _, _, warm, t_warm = ws.solve_family(fam, te, qpa.Settings(eps=1e-6), x0=x0, y0=y0, omega0=w0)
+    _, _, cold, t_cold = ws.solve_family(fam, te, s6, log=lambda msg: log(f"[bench] cold: {msg}"))
+    _, _, warm, t_warm = ws.solve_family(fam, te, s6, x0=x0, y0=y0, omega0=w0,
+                                         log=lambda msg: log(f"[bench] warm: {msg}"))
     ci = np.array([r["iterations"] for r in cold], dtype=float)
     wi = np.array([r["iterations"] for r in warm], dtype=float)
     kept = int(sum(r["used_warm_start"] for r in warm))

@@ -129,6 +129,13 @@ typedef struct {
                                 the gathered vector exceeds 2 MB, else 1), 1 = unpanelled,
                                 2/4/8 = panels pinned to groups of 8/np XCDs */
     int32_t panels_primal;   /* same for P = [Q | -A'] in the primal phase */
+    int32_t momentum;        /* 1 (default): accelerated PDHG, Algorithm 1 with beta_k = (k+2)/2,
+                                theta_k = k/(k+1) (Theorem 1); 0: plain PDHG, the Sec. 5
+                                baseline: beta = theta = 1, the constant step of the Sec. 6 rule
+                                at beta = 1, and the uniform average of the cycle's iterates as
+                                the average candidate.  Combined with restart_mode this gives
+                                the four methods of Sec. 5 (PDHG, restarted PDHG, accelerated
+                                PDHG = momentum 1 + QP_RESTART_NONE, rAPDHG). */
 } qp_settings;
 
 typedef struct {

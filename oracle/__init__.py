@@ -2,7 +2,8 @@
 
 A plain, sequential, FP64 implementation of restarted accelerated PDHG for
 convex QP (Lu & Yang, arXiv 2311.07710: Algorithm 1, Sec. 5 progress metric
-and restart, Sec. 6 adaptive step size / primal weight / restart), written in
+and restart, Sec. 6 adaptive step size / primal weight / restart, the Sec. 5
+diagonal preconditioning and the Sec. 5 PDHG baselines), written in
 C (``rapdhg_oracle.c``) and wrapped with ctypes here.
 
 Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may use
@@ -27,4 +28,6 @@ from .oracle import (  # noqa: F401
     step_schedule,
     run_inner,
     solve,
+    precondition,
+    solve_scaled,
 )

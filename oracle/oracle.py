@@ -37,7 +37,7 @@ class _Settings(C.Structure):
                 ("eps_zero", C.c_double), ("step_safety", C.c_double),
                 ("norm_A", C.c_double), ("norm_Q", C.c_double),
                 ("power_iter_max", C.c_int32), ("power_iter_rtol", C.c_double),
-                ("warm_fallback", C.c_int32)]
+                ("warm_fallback", C.c_int32), ("momentum", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -79,6 +79,7 @@ class OracleSettings:
     power_iter_max: int = 1000
     power_iter_rtol: float = 1e-7
     warm_fallback: int = 1
+    momentum: int = 1
 
     def _c(self) -> _Settings:
         s = _Settings()
@@ -112,6 +113,14 @@ def load():
                                   _pd, _pd, C.POINTER(_Result), C.POINTER(_CheckLog), C.c_int64,
                                   C.POINTER(C.c_int64)]
         lib.orc_solve.restype = C.c_int
+        lib.orc_precondition.argtypes = [C.POINTER(_Problem), C.c_int32, C.c_int32, C.c_int32,
+                                         _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pd]
+        lib.orc_precondition.restype = None
+        lib.orc_solve_scaled.argtypes = [C.POINTER(_Problem), C.POINTER(_Problem), _pd, _pd,
+                                         C.POINTER(_Settings), _pd, _pd, C.c_double, _pd, _pd,
+                                         C.POINTER(_Result), C.POINTER(_CheckLog), C.c_int64,
+                                         C.POINTER(C.c_int64)]
+        lib.orc_solve_scaled.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -218,8 +227,31 @@ def run_inner(qp, settings: OracleSettings, nA, nQ, omega, iters, x0=None, y0=No
     return x, y[:qp.m], xb, yb[:qp.m]
 
 
+def precondition(qp, ruiz_iters=10, l2=True, pc=True):
+    """Diagonal preconditioning of K = [[Q, A'], [A, 0]]; returns (scaled instance,
+    D2 [n], D1 [m]) with Q~ = D2 Q D2, A~ = D1 A D2, c~ = D2 c, b~ = D1 b, bounds / D2."""
+    import dataclasses
+    pr = _ProblemRef(qp)
+    qv = np.zeros(max(len(qp.q_val), 1))
+    av = np.zeros(max(len(qp.a_val), 1))
+    c = np.zeros(qp.n); l = np.zeros(qp.n); u = np.zeros(qp.n)
+    b = np.zeros(max(qp.m, 1)); dv = np.zeros(qp.n); dr = np.zeros(max(qp.m, 1))
+    load().orc_precondition(C.byref(pr.s), int(ruiz_iters), int(bool(l2)), int(bool(pc)),
+                            _ptr(qv, _pd), _ptr(av, _pd), _ptr(c, _pd), _ptr(b, _pd),
+                            _ptr(l, _pd), _ptr(u, _pd), _ptr(dv, _pd), _ptr(dr, _pd))
+    scaled = dataclasses.replace(qp, q_val=qv[:len(qp.q_val)], a_val=av[:len(qp.a_val)], c=c,
+                                 b=b[:qp.m], l=l, u=u)
+    return scaled, dv, dr[:qp.m]
+
+
+def solve_scaled(scaled, orig, d_var, d_row, settings: OracleSettings | None = None, x0=None,
+                 y0=None, omega0=0.0, log_cap: int = 0):
+    """Solve the preconditioned instance; relKKT, warm starts and outputs refer to orig."""
+    return solve(scaled, settings, x0, y0, omega0, log_cap, _orig=(orig, d_var, d_row))
+
+
 def solve(qp, settings: OracleSettings | None = None, x0=None, y0=None, omega0=0.0,
-          log_cap: int = 0):
+          log_cap: int = 0, _orig=None):
     """Run the oracle; returns (x, y, result dict, check log list)."""
     settings = settings or OracleSettings()
     pr = _ProblemRef(qp)
@@ -232,11 +264,19 @@ def solve(qp, settings: OracleSettings | None = None, x0=None, y0=None, omega0=0
     y0p = _f64(y0) if y0 is not None else None
     if y0p is not None and y0p.size == 0:
         y0p = np.zeros(1)
-    rc = load().orc_solve(C.byref(pr.s), C.byref(settings._c()),
-                          _ptr(x0p, _pd) if x0p is not None else None,
-                          _ptr(y0p, _pd) if y0p is not None else None,
-                          float(omega0), _ptr(x, _pd), _ptr(y, _pd), C.byref(res),
-                          logs if log_cap > 0 else None, log_cap, C.byref(nlog))
+    tail = (_ptr(x0p, _pd) if x0p is not None else None,
+            _ptr(y0p, _pd) if y0p is not None else None,
+            float(omega0), _ptr(x, _pd), _ptr(y, _pd), C.byref(res),
+            logs if log_cap > 0 else None, log_cap, C.byref(nlog))
+    if _orig is None:
+        rc = load().orc_solve(C.byref(pr.s), C.byref(settings._c()), *tail)
+    else:
+        orig, dv, dr = _orig
+        po = _ProblemRef(orig)
+        dv = _f64(dv)
+        dr = _f64(dr) if orig.m else np.ones(1)
+        rc = load().orc_solve_scaled(C.byref(pr.s), C.byref(po.s), _ptr(dv, _pd), _ptr(dr, _pd),
+                                     C.byref(settings._c()), *tail)
     if rc != 0:
         raise ValueError(f"oracle rejected the problem (rc={rc}, status={res.status})")
     r = {name: getattr(res, name) for name, _ in _Result._fields_}

@@ -7,7 +7,9 @@
  *     parameters of Theorem 1 / eq. (param-choice) for beta_k and theta_k;
  *   - adaptive restart, step size and primal weight: Sec. 6 (PDQP.jl);
  *   - progress metric and termination: Sec. 5 (relative KKT error);
- *   - fixed-frequency and "halving" restarts: Algorithm 1 and Sec. 5.
+ *   - fixed-frequency and "halving" restarts: Algorithm 1 and Sec. 5;
+ *   - the Sec. 5 baselines: PDHG without momentum (beta = theta = 1) with and
+ *     without restarts.
  * Everything is sequential and unblocked: each row sum runs in CSR order,
  * each dot product runs from index 0 upward.
  */
@@ -43,6 +45,7 @@ void orc_default_settings(orc_settings *s) {
     s->power_iter_max = 1000;
     s->power_iter_rtol = 1e-7;
     s->warm_fallback = 1;
+    s->momentum = 1;
 }
 
 /* ------------------------------------------------------------------ */
@@ -226,6 +229,16 @@ static double pdqp_cap(const orc_settings *s, double nA, double nQ, double w, in
  * s_{k-1} of the same cycle (ignored at k = 0) and is updated to s_k. */
 static void step_at(const orc_settings *s, double nA, double nQ, double omega, int64_t k,
                     double *s_last, double *p, double *d) {
+    if (!s->momentum) {
+        /* plain PDHG: beta = 1 in the step condition 1/p - ||Q||/beta - ||A||^2 d >= 0,
+         * i.e. the Sec. 6 cap with (k+2) replaced by 2, held constant over the cycle */
+        double qw = nQ / omega;
+        double sk = s->step_safety * 2.0 / (qw + sqrt(4.0 * nA * nA + qw * qw));
+        *s_last = sk;
+        *p = sk / omega;
+        *d = sk * omega;
+        return;
+    }
     if (s->restart_mode == ORC_RESTART_FIXED_K) {
         /* Theorem 1 / eq. (param-choice): eta_k = (k+1)/(2(||Q|| + K||A||)),
          * tau_k = (k+1)/(2 K ||A||) with K the restart frequency */
@@ -279,13 +292,25 @@ static void state_free(orc_state *st) {
     free(st->g); free(st->aty); free(st->y); free(st->ybar); free(st->ax);
 }
 
-/* One iteration with inner index k, primal step pk, dual step dk. */
-static void one_iteration(const orc_problem *p, orc_state *st, int64_t k, double pk, double dk) {
+/* One iteration with inner index k, primal step pk, dual step dk.
+ * Accelerated (Algorithm 1 with Theorem 1's weights): beta_k = (k+2)/2,
+ * theta_k = k/(k+1); the running average z-bar takes weight 1/beta_k.
+ * Plain PDHG (momentum = 0): beta = theta = 1, so Q is applied at x itself and
+ * x~ = 2x - x_prev; z-bar is then the uniform average of the iterates of the
+ * cycle (weight 1/(k+1)), the candidate of restarted PDHG. */
+static void one_iteration(const orc_problem *p, orc_state *st, int momentum, int64_t k,
+                          double pk, double dk) {
     const int64_t n = p->n, m = p->m;
-    double beta = (double)(k + 2) / 2.0;      /* beta_k = (k+2)/2 */
-    double w = 2.0 / (double)(k + 2);         /* 1/beta_k */
-    double theta = (double)k / (double)(k + 1); /* theta_k = k/(k+1) */
-    (void)beta;
+    double w, theta, a;
+    if (momentum) {
+        w = 2.0 / (double)(k + 2);              /* 1/beta_k */
+        theta = (double)k / (double)(k + 1);    /* theta_k */
+        a = w;
+    } else {
+        w = 1.0;
+        theta = 1.0;
+        a = 1.0 / (double)(k + 1);
+    }
     /* x_md = (1 - 1/beta) xbar + (1/beta) x ;  x~ = x + theta (x - x_prev) */
     for (int64_t j = 0; j < n; ++j) {
         st->xmd[j] = (1.0 - w) * st->xbar[j] + w * st->x[j];
@@ -305,9 +330,9 @@ static void one_iteration(const orc_problem *p, orc_state *st, int64_t k, double
         double xn = proj_box(st->x[j] - pk * grad, p->l[j], p->u[j]);
         st->x_prev[j] = st->x[j];
         st->x[j] = xn;
-        st->xbar[j] = (1.0 - w) * st->xbar[j] + w * xn;
+        st->xbar[j] = (1.0 - a) * st->xbar[j] + a * xn;
     }
-    for (int64_t i = 0; i < m; ++i) st->ybar[i] = (1.0 - w) * st->ybar[i] + w * st->y[i];
+    for (int64_t i = 0; i < m; ++i) st->ybar[i] = (1.0 - a) * st->ybar[i] + a * st->y[i];
 }
 
 void orc_run_inner(const orc_problem *p, const orc_settings *s, double nA, double nQ,
@@ -324,7 +349,7 @@ void orc_run_inner(const orc_problem *p, const orc_settings *s, double nA, doubl
     double *pk = malloc(sizeof(double) * (size_t)(iters > 0 ? iters : 1));
     double *dk = malloc(sizeof(double) * (size_t)(iters > 0 ? iters : 1));
     orc_step_schedule(s, nA, nQ, omega, iters, pk, dk, NULL);
-    for (int64_t k = 0; k < iters; ++k) one_iteration(p, &st, k, pk[k], dk[k]);
+    for (int64_t k = 0; k < iters; ++k) one_iteration(p, &st, s->momentum, k, pk[k], dk[k]);
     memcpy(x, st.x, sizeof(double) * (size_t)p->n);
     memcpy(xbar, st.xbar, sizeof(double) * (size_t)p->n);
     if (p->m) {
@@ -338,9 +363,26 @@ void orc_run_inner(const orc_problem *p, const orc_settings *s, double nA, doubl
 /* ------------------------------------------------------------------ */
 /* full solve: Algorithm 1 inner loop + Sec. 6 / Sec. 5 restart rules  */
 /* ------------------------------------------------------------------ */
-int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, const double *y0,
-              double omega0, double *x_out, double *y_out, orc_result *res,
-              orc_check_log *check_log, int64_t log_cap, int64_t *log_len) {
+/* relKKT of (x, y).  Unscaled problem: directly.  Preconditioned problem: the point
+ * is mapped back, x = D2 x~, y = D1 y~ (xu, yu are n- and m-sized work arrays), and
+ * the error is that of the original problem (Sec. 5 measures the given instance). */
+static void kkt_eval(const orc_problem *p, const orc_problem *orig, const double *dv,
+                     const double *dr, const double *x, const double *y, double *xu, double *yu,
+                     orc_kkt *out) {
+    if (!orig) {
+        orc_rel_kkt(p, x, y, out);
+        return;
+    }
+    for (int64_t j = 0; j < p->n; ++j) xu[j] = x[j] * dv[j];
+    for (int64_t i = 0; i < p->m; ++i) yu[i] = y[i] * dr[i];
+    orc_rel_kkt(orig, xu, yu, out);
+}
+
+static int solve_impl(const orc_problem *p, const orc_problem *orig, const double *dv,
+                      const double *dr, const orc_settings *s, const double *x0,
+                      const double *y0, double omega0, double *x_out, double *y_out,
+                      orc_result *res, orc_check_log *check_log, int64_t log_cap,
+                      int64_t *log_len) {
     const int64_t n = p->n, m = p->m;
     const double t_start = now_s();
     memset(res, 0, sizeof(*res));
@@ -360,6 +402,8 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
 
     orc_state st;
     state_alloc(&st, n, m);
+    double *xu = malloc(sizeof(double) * (size_t)n);
+    double *yu = malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
     double *x_rs = malloc(sizeof(double) * (size_t)n);
     double *y_rs = malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
     double s_last = 0.0; /* PDQP scale s_{k-1} of the current cycle */
@@ -378,8 +422,8 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
         int take = 1;
         if (s->warm_fallback) {
             orc_kkt kw, kc;
-            orc_rel_kkt(p, xw, yw, &kw);
-            orc_rel_kkt(p, st.x, st.y, &kc);
+            kkt_eval(p, orig, dv, dr, xw, yw, xu, yu, &kw);
+            kkt_eval(p, orig, dv, dr, st.x, st.y, xu, yu, &kc);
             kkt_evals += 2;
             take = kw.rel_kkt < kc.rel_kkt;
         }
@@ -405,7 +449,7 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
         omega = (nc > s->eps_zero && nb > s->eps_zero) ? nc / nb : 1.0;
     }
 
-    orc_rel_kkt(p, st.x, st.y, &kk);
+    kkt_eval(p, orig, dv, dr, st.x, st.y, xu, yu, &kk);
     kkt_evals += 1;
     double r0 = kk.rel_kkt;
     double prev_cand = INFINITY;
@@ -424,13 +468,13 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
         for (int64_t j = 0; j < len; ++j) {
             double pkj, dkj;
             step_at(s, nA, nQ, omega, k, &s_last, &pkj, &dkj);
-            one_iteration(p, &st, k, pkj, dkj);
+            one_iteration(p, &st, s->momentum, k, pkj, dkj);
             ++k; ++total;
         }
         /* evaluation */
         orc_kkt kcur, kavg;
-        orc_rel_kkt(p, st.x, st.y, &kcur);
-        orc_rel_kkt(p, st.xbar, st.ybar, &kavg);
+        kkt_eval(p, orig, dv, dr, st.x, st.y, xu, yu, &kcur);
+        kkt_eval(p, orig, dv, dr, st.xbar, st.ybar, xu, yu, &kavg);
         kkt_evals += 2;
         double r = kcur.rel_kkt, rb = kavg.rel_kkt;
         int cand_avg;
@@ -509,8 +553,8 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
 
     const double *xs = from_avg ? st.xbar : st.x;
     const double *ys = from_avg ? st.ybar : st.y;
-    memcpy(x_out, xs, sizeof(double) * (size_t)n);
-    if (m) memcpy(y_out, ys, sizeof(double) * (size_t)m);
+    for (int64_t j = 0; j < n; ++j) x_out[j] = orig ? xs[j] * dv[j] : xs[j];
+    for (int64_t i = 0; i < m; ++i) y_out[i] = orig ? ys[i] * dr[i] : ys[i];
     res->status = status;
     res->iterations = total;
     res->restarts = restarts;
@@ -524,7 +568,134 @@ int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, con
     res->omega = omega;
     res->used_warm_start = used_warm;
     if (log_len) *log_len = nlog < log_cap ? nlog : log_cap;
-    free(x_rs); free(y_rs);
+    free(x_rs); free(y_rs); free(xu); free(yu);
     state_free(&st);
     return 0;
+}
+
+int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, const double *y0,
+              double omega0, double *x_out, double *y_out, orc_result *res,
+              orc_check_log *check_log, int64_t log_cap, int64_t *log_len) {
+    return solve_impl(p, NULL, NULL, NULL, s, x0, y0, omega0, x_out, y_out, res, check_log,
+                      log_cap, log_len);
+}
+
+int orc_solve_scaled(const orc_problem *scaled, const orc_problem *orig, const double *d_var,
+                     const double *d_row, const orc_settings *s, const double *x0,
+                     const double *y0, double omega0, double *x_out, double *y_out,
+                     orc_result *res, orc_check_log *check_log, int64_t log_cap,
+                     int64_t *log_len) {
+    const int64_t n = scaled->n, m = scaled->m;
+    double *xs0 = NULL, *ys0 = NULL;
+    if (x0) {
+        xs0 = malloc(sizeof(double) * (size_t)n);
+        for (int64_t j = 0; j < n; ++j) xs0[j] = x0[j] / d_var[j];
+    }
+    if (y0) {
+        ys0 = malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+        for (int64_t i = 0; i < m; ++i) ys0[i] = y0[i] / d_row[i];
+    }
+    int rc = solve_impl(scaled, orig, d_var, d_row, s, xs0, ys0, omega0, x_out, y_out, res,
+                        check_log, log_cap, log_len);
+    free(xs0);
+    free(ys0);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* diagonal preconditioning (Sec. 5 "Preprocessing", also used by      */
+/* Sec. 6): symmetric scaling of K = [[Q, A'], [A, 0]]                  */
+/* ------------------------------------------------------------------ */
+/* Row statistic of every row of K at the current values: kind 0 = max |k|,
+ * 1 = sqrt(sum k^2), 2 = sum |k|.  Variable row j of K is Q's row j (stored
+ * order) followed by A's column j (increasing row index); constraint row i of K is
+ * A's row i (stored order). */
+static void k_row_stat(const orc_problem *p, const double *qv, const double *av, int kind,
+                       double *st) {
+    const int64_t n = p->n, m = p->m;
+    for (int64_t j = 0; j < n; ++j) {
+        double a = 0.0;
+        for (int64_t e = p->q_rowptr[j]; e < p->q_rowptr[j + 1]; ++e) {
+            double v = fabs(qv[e]);
+            if (kind == 0) a = v > a ? v : a;
+            else if (kind == 1) a = a + v * v;
+            else a = a + v;
+        }
+        st[j] = a;
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        double a = 0.0;
+        for (int64_t e = p->a_rowptr[i]; e < p->a_rowptr[i + 1]; ++e) {
+            double v = fabs(av[e]);
+            int64_t j = p->a_col[e];
+            if (kind == 0) {
+                a = v > a ? v : a;
+                st[j] = v > st[j] ? v : st[j];
+            } else if (kind == 1) {
+                a = a + v * v;
+                st[j] = st[j] + v * v;
+            } else {
+                a = a + v;
+                st[j] = st[j] + v;
+            }
+        }
+        st[n + i] = a;
+    }
+    if (kind == 1)
+        for (int64_t r = 0; r < n + m; ++r) st[r] = sqrt(st[r]);
+}
+
+/* One scaling step: f_r = 1/sqrt(stat_r) (1 for an empty row), K <- diag(f) K diag(f)
+ * entry by entry as k * (f_r * f_c), d <- d * f. */
+static void k_scale_step(const orc_problem *p, double *qv, double *av, const double *st,
+                         double *f, double *d) {
+    const int64_t n = p->n, m = p->m;
+    for (int64_t r = 0; r < n + m; ++r) {
+        f[r] = st[r] > 0.0 ? 1.0 / sqrt(st[r]) : 1.0;
+        d[r] = d[r] * f[r];
+    }
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t e = p->q_rowptr[j]; e < p->q_rowptr[j + 1]; ++e)
+            qv[e] = qv[e] * (f[j] * f[p->q_col[e]]);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t e = p->a_rowptr[i]; e < p->a_rowptr[i + 1]; ++e)
+            av[e] = av[e] * (f[n + i] * f[p->a_col[e]]);
+}
+
+void orc_precondition(const orc_problem *p, int32_t ruiz_iters, int32_t l2, int32_t pc,
+                      double *q_val, double *a_val, double *c, double *b, double *l, double *u,
+                      double *d_var, double *d_row) {
+    const int64_t n = p->n, m = p->m;
+    const int64_t qn = p->q_rowptr[n], an = m > 0 ? p->a_rowptr[m] : 0;
+    double *st = malloc(sizeof(double) * (size_t)(n + m));
+    double *f = malloc(sizeof(double) * (size_t)(n + m));
+    double *d = malloc(sizeof(double) * (size_t)(n + m));
+    memcpy(q_val, p->q_val, sizeof(double) * (size_t)qn);
+    if (an) memcpy(a_val, p->a_val, sizeof(double) * (size_t)an);
+    for (int64_t r = 0; r < n + m; ++r) d[r] = 1.0;
+    for (int32_t t = 0; t < ruiz_iters; ++t) {   /* Ruiz: infinity-norm equilibration */
+        k_row_stat(p, q_val, a_val, 0, st);
+        k_scale_step(p, q_val, a_val, st, f, d);
+    }
+    if (l2) {                                      /* l2-norm scaling */
+        k_row_stat(p, q_val, a_val, 1, st);
+        k_scale_step(p, q_val, a_val, st, f, d);
+    }
+    if (pc) {   /* Pock-Chambolle, alpha = 1: rows by sum |k|^alpha, columns by
+                   sum |k|^(2-alpha); K is symmetric, so both are the row sums */
+        k_row_stat(p, q_val, a_val, 2, st);
+        k_scale_step(p, q_val, a_val, st, f, d);
+    }
+    /* x = D2 x~, y = D1 y~:  c~ = D2 c, b~ = D1 b, bounds l/D2, u/D2 */
+    for (int64_t j = 0; j < n; ++j) {
+        d_var[j] = d[j];
+        c[j] = p->c[j] * d[j];
+        l[j] = p->l[j] / d[j];
+        u[j] = p->u[j] / d[j];
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        d_row[i] = d[n + i];
+        b[i] = p->b[i] * d[n + i];
+    }
+    free(st); free(f); free(d);
 }

@@ -50,6 +50,9 @@ typedef struct {
     int32_t power_iter_max;
     double power_iter_rtol;
     int32_t warm_fallback;   /* 1: keep the warm start only if its relKKT beats the cold start's */
+    int32_t momentum;        /* 1: accelerated PDHG weights of Algorithm 1 (default);
+                                0: plain PDHG, the Sec. 5 baseline (beta = theta = 1, constant
+                                step, uniform average of the cycle as restart candidate) */
 } orc_settings;
 
 typedef struct {
@@ -94,7 +97,8 @@ double orc_norm_Q(const orc_problem *p, int32_t maxit, double rtol, int32_t *ite
 void orc_step_schedule(const orc_settings *s, double norm_A, double norm_Q, double omega,
                        int64_t K, double *p, double *d, double *scale);
 
-/* Run exactly `iters` inner iterations of accelerated PDHG (no restart, no check)
+/* Run exactly `iters` inner iterations of (accelerated, unless s->momentum == 0) PDHG
+ * (no restart, no check)
  * from (x,y) with the schedule of `s` at primal weight omega.  On return x,y hold
  * the last iterate and xbar,ybar the running averages. */
 void orc_run_inner(const orc_problem *p, const orc_settings *s, double norm_A, double norm_Q,
@@ -105,6 +109,25 @@ void orc_run_inner(const orc_problem *p, const orc_settings *s, double norm_A, d
 int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, const double *y0,
               double omega0, double *x_out, double *y_out, orc_result *res,
               orc_check_log *check_log, int64_t log_cap, int64_t *log_len);
+
+/* Diagonal preconditioning (Sec. 5 "Preprocessing"): ruiz_iters infinity-norm
+ * (Ruiz) steps, then one l2-norm step if l2, then one Pock-Chambolle (alpha = 1)
+ * step if pc, all on K = [[Q, A'], [A, 0]] with one symmetric diagonal scaling
+ * d = (D2, D1).  Writes the scaled values (same sparsity as p): Q~ = D2 Q D2,
+ * A~ = D1 A D2, c~ = D2 c, b~ = D1 b, l~ = l / D2, u~ = u / D2, and D2 (d_var, n),
+ * D1 (d_row, m).  Solutions map back as x = D2 x~, y = D1 y~. */
+void orc_precondition(const orc_problem *p, int32_t ruiz_iters, int32_t l2, int32_t pc,
+                      double *q_val, double *a_val, double *c, double *b, double *l, double *u,
+                      double *d_var, double *d_row);
+
+/* Solve of a preconditioned problem: iterates live in the scaled space, every
+ * relKKT is that of the original problem at (D2 x~, D1 y~); warm starts and
+ * outputs are in the original space. */
+int orc_solve_scaled(const orc_problem *scaled, const orc_problem *orig, const double *d_var,
+                     const double *d_row, const orc_settings *s, const double *x0,
+                     const double *y0, double omega0, double *x_out, double *y_out,
+                     orc_result *res, orc_check_log *check_log, int64_t log_cap,
+                     int64_t *log_len);
 
 #ifdef __cplusplus
 }

@@ -47,7 +47,8 @@ class qp_settings(C.Structure):
                 ("norm_Q", C.c_double), ("power_iter_max", C.c_int32),
                 ("power_iter_rtol", C.c_double), ("warm_fallback", C.c_int32),
                 ("use_graph", C.c_int32), ("profile", C.c_int32), ("log_checks", C.c_int32),
-                ("device", C.c_int32), ("panels_dual", C.c_int32), ("panels_primal", C.c_int32)]
+                ("device", C.c_int32), ("panels_dual", C.c_int32), ("panels_primal", C.c_int32),
+                ("momentum", C.c_int32)]
 
 
 class qp_warm_start(C.Structure):

@@ -410,6 +410,7 @@ void qp_default_settings(qp_settings *s) {
     s->device = 0;
     s->panels_dual = 0;
     s->panels_primal = 0;
+    s->momentum = 1;
 }
 
 const char *qp_last_error(void) { return qph::g_err.c_str(); }
@@ -430,6 +431,8 @@ int check_settings(const qp_settings &s) {
     if (s.check_every > 4096 || (s.restart_mode == QP_RESTART_FIXED_K && s.fixed_K > 4096))
         return fail(QP_ERR_INVALID_ARGUMENT, "evaluation interval above 4096 is not supported");
     if (!(s.step_safety > 0.0)) return fail(QP_ERR_INVALID_ARGUMENT, "step_safety must be > 0");
+    if (s.momentum != 0 && s.momentum != 1)
+        return fail(QP_ERR_INVALID_ARGUMENT, "momentum must be 0 or 1");
     return QP_OK;
 }
 
@@ -616,12 +619,7 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
             pv[pos] = -av[e];
         }
 
-    auto up = [&](DevMem &dm, const void *src, size_t bytes) -> int {
-        int r2 = dm.alloc(std::max<size_t>(bytes, 8));
-        if (r2) return r2;
-        if (bytes) HIPCHK(hipMemcpy(dm.p, src, bytes, hipMemcpyHostToDevice));
-        return QP_OK;
-    };
+    auto up = [&](DevMem &dm, const void *src, size_t bytes) -> int { return dm.upload(src, bytes); };
     if ((rc = up(h->a_rowptr, ar.data(), ar.size() * 4)) || (rc = up(h->a_col, ac.data(), ac.size() * 4)) ||
         (rc = up(h->a_val, av.data(), av.size() * 8)) || (rc = up(h->p_rowptr, pr.data(), pr.size() * 4)) ||
         (rc = up(h->p_col, pc.data(), pc.size() * 4)) || (rc = up(h->p_val, pv.data(), pv.size() * 8)) ||
@@ -673,8 +671,8 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
         return rc;
     h->nslotA = h->partA.view.nblk + h->partA.view.nlr;
     h->nslotP = h->partP.view.nblk + h->partP.view.nlr;
-    if ((rc = h->partials_a.alloc((size_t)std::max(h->nslotA, 1) * RA_NV * 8)) ||
-        (rc = h->partials_p.alloc((size_t)std::max(h->nslotP, 1) * RP_NV * 8)) ||
+    if ((rc = h->partials_a.alloc((size_t)(h->nslotA + FOLD_SLOTS) * RA_NV * 8)) ||
+        (rc = h->partials_p.alloc((size_t)(h->nslotP + FOLD_SLOTS) * RP_NV * 8)) ||
         (rc = h->state.alloc(sizeof(State))) || (rc = h->table.alloc(4096 * sizeof(Step))))
         return rc;
     Vecs &v = h->vecs;
@@ -714,6 +712,7 @@ DevSettings dev_settings(const qp_handle *h) {
     ds.restart_mode = s.restart_mode;
     ds.fixed_K = s.fixed_K;
     ds.interval = s.restart_mode == QP_RESTART_FIXED_K ? s.fixed_K : s.check_every;
+    ds.momentum = s.momentum;
     return ds;
 }
 

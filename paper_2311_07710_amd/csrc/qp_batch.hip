@@ -62,7 +62,12 @@ struct BatchDev {
     int64_t deadline_ticks;  // 0: no time limit
     int32_t warm_fallback, any_warm;
     int32_t lds_doubles;     // dynamic LDS per team (doubles); 0: gathered vectors in HBM
+    // rows longer than LONG_ROW nonzeros are reduced by the whole team
+    const int32_t *lrA_off, *lrA;  // per instance [off[i], off[i+1]) into local A row ids
+    const int32_t *lrP_off, *lrP;  // same for rows of P
 };
+
+constexpr int LONG_ROW = 128;
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -96,16 +101,112 @@ __device__ void team_reduce(double *cv, int nv, int nmax_first, double *red /*[3
     __syncthreads();
 }
 
-// KKT quantities of z = (x, y) and z-bar for one instance; results in thread 0's ra/rp
+// sums of W values over the team, valid in thread 0 (fixed order)
+template <int NT, int W>
+__device__ void team_sum(double *v, double *red) {
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int q = 0; q < W; ++q) {
+        double x = v[q];
+        for (int off = 32; off >= 1; off >>= 1) x = x + __shfl_xor(x, off, 64);
+        if (lane == 0) red[q * (NT / 64) + wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < W; ++q) {
+            double acc = red[q * (NT / 64)];
+            for (int w = 1; w < NT / 64; ++w) acc = acc + red[q * (NT / 64) + w];
+            v[q] = acc;
+        }
+    __syncthreads();
+}
+
+// per-row KKT contributions (rows of A: primal residuals, |Ax|, b'y, restart distances)
+__device__ __forceinline__ void kkt_row_contrib(int i, double s0, double s1, const double *b,
+                                                const uint8_t *rt, const double *y,
+                                                const double *ybar, const double *yrs,
+                                                double *ra) {
+    const double bi = b[i];
+    double r0 = s0 - bi, r1 = s1 - bi;
+    if (rt[i] == 1) {
+        r0 = (r0 < 0.0) ? -r0 : 0.0;
+        r1 = (r1 < 0.0) ? -r1 : 0.0;
+    }
+    ra[RA_RES0] = bmax(ra[RA_RES0], fabs(r0));
+    ra[RA_RES1] = bmax(ra[RA_RES1], fabs(r1));
+    ra[RA_AX0] = bmax(ra[RA_AX0], fabs(s0));
+    ra[RA_AX1] = bmax(ra[RA_AX1], fabs(s1));
+    const double yi = y[i], ybi = ybar[i], yr = yrs[i];
+    ra[RA_BY0] += bi * yi;
+    ra[RA_BY1] += bi * ybi;
+    const double d0 = yi - yr, d1 = ybi - yr;
+    ra[RA_DY0] += d0 * d0;
+    ra[RA_DY1] += d1 * d1;
+}
+
+// per-column KKT contributions (rows of P: reduced costs, |Qx|, |A'y|, x'Qx, c'x, bound terms)
+__device__ __forceinline__ void kkt_col_contrib(int j, const double *q, const double *na,
+                                                const double *c, const double *l,
+                                                const double *u, const double *x,
+                                                const double *xbar, const double *xrs,
+                                                double *rp) {
+    const double cj = c[j], lj = l[j], uj = u[j];
+    const bool lo_fin = isfinite(lj), hi_fin = isfinite(uj);
+    for (int p = 0; p < 2; ++p) {
+        const double xp = p == 0 ? x[j] : xbar[j];
+        const double aty = -na[p];
+        const double lam = q[p] + cj - aty;
+        double lam_hat;
+        if (lo_fin && hi_fin) lam_hat = lam;
+        else if (lo_fin) lam_hat = lam > 0.0 ? lam : 0.0;
+        else if (hi_fin) lam_hat = lam < 0.0 ? lam : 0.0;
+        else lam_hat = 0.0;
+        rp[RP_DRES0 + p] = bmax(rp[RP_DRES0 + p], fabs(lam - lam_hat));
+        rp[RP_QX0 + p] = bmax(rp[RP_QX0 + p], fabs(q[p]));
+        rp[RP_ATY0 + p] = bmax(rp[RP_ATY0 + p], fabs(aty));
+        rp[RP_XQX0 + p] += xp * q[p];
+        rp[RP_CX0 + p] += cj * xp;
+        double bnd = 0.0;
+        if (lo_fin && lam_hat > 0.0) bnd = lj * lam_hat;
+        if (hi_fin && lam_hat < 0.0) bnd = uj * lam_hat;
+        rp[RP_BND0 + p] += bnd;
+        const double dx = xp - xrs[j];
+        rp[RP_DX0 + p] += dx * dx;
+    }
+}
+
+// Sum of val[e] * src(col[e]) over e in [e0, e1), added in CSR order; the loads of
+// four entries are issued together so that their latencies overlap.
+template <class F>
+__device__ __forceinline__ double row_dot(const int32_t *__restrict__ col,
+                                          const double *__restrict__ val, int e0, int e1, F src) {
+    double s = 0.0;
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {
+        const int c0 = col[e], c1 = col[e + 1], c2 = col[e + 2], c3 = col[e + 3];
+        const double a0 = val[e], a1 = val[e + 1], a2 = val[e + 2], a3 = val[e + 3];
+        const double g0 = src(c0), g1 = src(c1), g2 = src(c2), g3 = src(c3);
+        s = s + a0 * g0;
+        s = s + a1 * g1;
+        s = s + a2 * g2;
+        s = s + a3 * g3;
+    }
+    for (; e < e1; ++e) s = s + val[e] * src(col[e]);
+    return s;
+}
+
+// KKT quantities of z = (x, y) and z-bar for one instance; results in thread 0's ra/rp.
+// Rows up to LONG_ROW nonzeros: one thread each; longer rows: the whole team.
 template <int NT>
 __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, const double *aval,
                          const int32_t *prp, const int32_t *pcol, const double *pval,
                          const double *c, const double *b, const double *l, const double *u,
                          const uint8_t *rt, const double *x, const double *xbar,
                          const double *xrs, const double *y, const double *ybar,
-                         const double *yrs, double *ra, double *rp, double *red) {
+                         const double *yrs, double *ra, double *rp, double *red,
+                         const int32_t *lra, int nlra, const int32_t *lrp, int nlrp) {
     for (int v = 0; v < RA_NV; ++v) ra[v] = 0.0;
     for (int i = threadIdx.x; i < m; i += NT) {
+        if (arp[i + 1] - arp[i] > LONG_ROW) continue;
         double s0 = 0.0, s1 = 0.0;
         for (int e = arp[i]; e < arp[i + 1]; ++e) {
             const int cc = acol[e];
@@ -113,26 +214,24 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
             s0 = s0 + a * x[cc];
             s1 = s1 + a * xbar[cc];
         }
-        const double bi = b[i];
-        double r0 = s0 - bi, r1 = s1 - bi;
-        if (rt[i] == 1) {
-            r0 = (r0 < 0.0) ? -r0 : 0.0;
-            r1 = (r1 < 0.0) ? -r1 : 0.0;
+        kkt_row_contrib(i, s0, s1, b, rt, y, ybar, yrs, ra);
+    }
+    for (int q = 0; q < nlra; ++q) {
+        const int i = lra[q];
+        double sv[2] = {0.0, 0.0};
+        for (int e = arp[i] + threadIdx.x; e < arp[i + 1]; e += NT) {
+            const int cc = acol[e];
+            const double a = aval[e];
+            sv[0] = sv[0] + a * x[cc];
+            sv[1] = sv[1] + a * xbar[cc];
         }
-        ra[RA_RES0] = bmax(ra[RA_RES0], fabs(r0));
-        ra[RA_RES1] = bmax(ra[RA_RES1], fabs(r1));
-        ra[RA_AX0] = bmax(ra[RA_AX0], fabs(s0));
-        ra[RA_AX1] = bmax(ra[RA_AX1], fabs(s1));
-        const double yi = y[i], ybi = ybar[i], yr = yrs[i];
-        ra[RA_BY0] += bi * yi;
-        ra[RA_BY1] += bi * ybi;
-        const double d0 = yi - yr, d1 = ybi - yr;
-        ra[RA_DY0] += d0 * d0;
-        ra[RA_DY1] += d1 * d1;
+        team_sum<NT, 2>(sv, red);
+        if (threadIdx.x == 0) kkt_row_contrib(i, sv[0], sv[1], b, rt, y, ybar, yrs, ra);
     }
     team_reduce<NT>(ra, RA_NV, 4, red);
     for (int v = 0; v < RP_NV; ++v) rp[v] = 0.0;
     for (int j = threadIdx.x; j < n; j += NT) {
+        if (prp[j + 1] - prp[j] > LONG_ROW) continue;
         double q[2] = {0.0, 0.0}, na[2] = {0.0, 0.0};
         for (int e = prp[j]; e < prp[j + 1]; ++e) {
             const int cc = pcol[e];
@@ -145,28 +244,26 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
                 na[1] = na[1] + a * ybar[cc - n];
             }
         }
-        const double cj = c[j], lj = l[j], uj = u[j];
-        const bool lo_fin = isfinite(lj), hi_fin = isfinite(uj);
-        for (int p = 0; p < 2; ++p) {
-            const double xp = p == 0 ? x[j] : xbar[j];
-            const double aty = -na[p];
-            const double lam = q[p] + cj - aty;
-            double lam_hat;
-            if (lo_fin && hi_fin) lam_hat = lam;
-            else if (lo_fin) lam_hat = lam > 0.0 ? lam : 0.0;
-            else if (hi_fin) lam_hat = lam < 0.0 ? lam : 0.0;
-            else lam_hat = 0.0;
-            rp[RP_DRES0 + p] = bmax(rp[RP_DRES0 + p], fabs(lam - lam_hat));
-            rp[RP_QX0 + p] = bmax(rp[RP_QX0 + p], fabs(q[p]));
-            rp[RP_ATY0 + p] = bmax(rp[RP_ATY0 + p], fabs(aty));
-            rp[RP_XQX0 + p] += xp * q[p];
-            rp[RP_CX0 + p] += cj * xp;
-            double bnd = 0.0;
-            if (lo_fin && lam_hat > 0.0) bnd = lj * lam_hat;
-            if (hi_fin && lam_hat < 0.0) bnd = uj * lam_hat;
-            rp[RP_BND0 + p] += bnd;
-            const double dx = xp - xrs[j];
-            rp[RP_DX0 + p] += dx * dx;
+        kkt_col_contrib(j, q, na, c, l, u, x, xbar, xrs, rp);
+    }
+    for (int qq = 0; qq < nlrp; ++qq) {
+        const int j = lrp[qq];
+        double sv[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int e = prp[j] + threadIdx.x; e < prp[j + 1]; e += NT) {
+            const int cc = pcol[e];
+            const double a = pval[e];
+            if (cc < n) {
+                sv[0] = sv[0] + a * x[cc];
+                sv[1] = sv[1] + a * xbar[cc];
+            } else {
+                sv[2] = sv[2] + a * y[cc - n];
+                sv[3] = sv[3] + a * ybar[cc - n];
+            }
+        }
+        team_sum<NT, 4>(sv, red);
+        if (threadIdx.x == 0) {
+            double q[2] = {sv[0], sv[1]}, na[2] = {sv[2], sv[3]};
+            kkt_col_contrib(j, q, na, c, l, u, x, xbar, xrs, rp);
         }
     }
     team_reduce<NT>(rp, RP_NV, 6, red);
@@ -178,6 +275,22 @@ __device__ __attribute__((noinline)) void batch_decide(int mode, const double *r
                                                        const double *rp, State *S,
                                                        const DevSettings *ds, int32_t len) {
     decide_update(mode, ra, rp, *S, *ds, len);
+}
+
+// projected primal step, x-bar averaging and the next x~ / x_md of row j
+__device__ __forceinline__ void primal_row(int j, double s, const Step &st, const double *c,
+                                           const double *l, const double *u, double *x,
+                                           double *xbar, double *xt, double *xout) {
+    const double g = s + c[j];
+    const double xo = x[j];
+    double xn = xo - st.p * g;
+    if (xn < l[j]) xn = l[j];
+    if (xn > u[j]) xn = u[j];
+    const double xb = (1.0 - st.w) * xbar[j] + st.w * xn;
+    x[j] = xn;
+    xbar[j] = xb;
+    xt[j] = xn + st.theta_next * (xn - xo);
+    xout[j] = (1.0 - st.w_next) * xb + st.w_next * xn;
 }
 
 __device__ __forceinline__ double proj_box_b(double v, double lo, double hi) {
@@ -215,6 +328,10 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
         double *xt = in_lds ? smem : a.xt + v0;
         double *xmd[2] = {in_lds ? smem + n : a.xmd0 + v0, in_lds ? smem + 2 * n : a.xmd1 + v0};
         double *y = in_lds ? smem + 3 * n : a.y + r0;
+        const int32_t *lra = a.lrA + a.lrA_off[id];
+        const int nlra = a.lrA_off[id + 1] - a.lrA_off[id];
+        const int32_t *lrp = a.lrP + a.lrP_off[id];
+        const int nlrp = a.lrP_off[id + 1] - a.lrP_off[id];
         DevSettings ds = base;
         ds.norm_A = a.normA[id];
         ds.norm_Q = a.normQ[id];
@@ -258,7 +375,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
         double ra[RA_NV], rp[RP_NV];
         if (pair) {
             team_kkt<NT>(n, m, arp, a.a_col, a.a_val, prp, a.p_col, a.p_val, c, b, l, u, rt, x,
-                         xbar, xrs, y, ybar, yrs, ra, rp, red);
+                         xbar, xrs, y, ybar, yrs, ra, rp, red, lra, nlra, lrp, nlrp);
             if (t == 0) batch_decide(DECIDE_FALLBACK, ra, rp, &S, &ds, 0);
             __syncthreads();
             const int take = S.used_warm;
@@ -273,7 +390,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
             __syncthreads();
         }
         team_kkt<NT>(n, m, arp, a.a_col, a.a_val, prp, a.p_col, a.p_val, c, b, l, u, rt, x, xbar,
-                     xrs, y, ybar, yrs, ra, rp, red);
+                     xrs, y, ybar, yrs, ra, rp, red, lra, nlra, lrp, nlrp);
         if (t == 0) {
             batch_decide(DECIDE_INIT, ra, rp, &S, &ds, 0);
             double sl = 0.0;
@@ -290,38 +407,48 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
                 const Step st = stp[sp];
                 // dual phase: y+ = proj_Y(y - d (A x~ - b)), y-bar averaging
                 for (int i = t; i < m; i += NT) {
-                    double s = 0.0;
-                    for (int e = arp[i]; e < arp[i + 1]; ++e) {
-                        const double prod = a.a_val[e] * xt[a.a_col[e]];
-                        s = s + prod;
-                    }
+                    if (arp[i + 1] - arp[i] > LONG_ROW) continue;
+                    const double s = row_dot(a.a_col, a.a_val, arp[i], arp[i + 1],
+                                             [&](int cc) { return xt[cc]; });
                     double yn = y[i] - st.d * (s - b[i]);
                     if (rt[i] == 1 && yn < 0.0) yn = 0.0;
                     ybar[i] = (1.0 - st.w) * ybar[i] + st.w * yn;
                     y[i] = yn;
+                }
+                for (int q = 0; q < nlra; ++q) {  // long rows: team-wide sum
+                    const int i = lra[q];
+                    double sv[1] = {0.0};
+                    for (int e = arp[i] + t; e < arp[i + 1]; e += NT)
+                        sv[0] = sv[0] + a.a_val[e] * xt[a.a_col[e]];
+                    team_sum<NT, 1>(sv, red);
+                    if (t == 0) {
+                        double yn = y[i] - st.d * (sv[0] - b[i]);
+                        if (rt[i] == 1 && yn < 0.0) yn = 0.0;
+                        ybar[i] = (1.0 - st.w) * ybar[i] + st.w * yn;
+                        y[i] = yn;
+                    }
                 }
                 __syncthreads();
                 // primal phase over P = [Q | -A'] gathering (x_md, y+)
                 const double *xin = xmd[md];
                 double *xout = xmd[md ^ 1];
                 for (int jj = t; jj < n; jj += NT) {
-                    double s = 0.0;
-                    for (int e = prp[jj]; e < prp[jj + 1]; ++e) {
+                    if (prp[jj + 1] - prp[jj] > LONG_ROW) continue;
+                    const double s = row_dot(a.p_col, a.p_val, prp[jj], prp[jj + 1], [&](int cc) {
+                        return *(cc < n ? xin + cc : y + (cc - n));
+                    });
+                    primal_row(jj, s, st, c, l, u, x, xbar, xt, xout);
+                }
+                for (int q = 0; q < nlrp; ++q) {  // long rows: team-wide sum
+                    const int jj = lrp[q];
+                    double sv[1] = {0.0};
+                    for (int e = prp[jj] + t; e < prp[jj + 1]; e += NT) {
                         const int cc = a.p_col[e];
                         const double v = cc < n ? xin[cc] : y[cc - n];
-                        const double prod = a.p_val[e] * v;
-                        s = s + prod;
+                        sv[0] = sv[0] + a.p_val[e] * v;
                     }
-                    const double g = s + c[jj];
-                    const double xo = x[jj];
-                    double xn = xo - st.p * g;
-                    if (xn < l[jj]) xn = l[jj];
-                    if (xn > u[jj]) xn = u[jj];
-                    const double xb = (1.0 - st.w) * xbar[jj] + st.w * xn;
-                    x[jj] = xn;
-                    xbar[jj] = xb;
-                    xt[jj] = xn + st.theta_next * (xn - xo);
-                    xout[jj] = (1.0 - st.w_next) * xb + st.w_next * xn;
+                    team_sum<NT, 1>(sv, red);
+                    if (t == 0) primal_row(jj, sv[0], st, c, l, u, x, xbar, xt, xout);
                 }
                 if (t == 0) {
                     double sl = s_last;
@@ -333,7 +460,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
                 md ^= 1;
             }
             team_kkt<NT>(n, m, arp, a.a_col, a.a_val, prp, a.p_col, a.p_val, c, b, l, u, rt, x,
-                         xbar, xrs, y, ybar, yrs, ra, rp, red);
+                         xbar, xrs, y, ybar, yrs, ra, rp, red, lra, nlra, lrp, nlrp);
             if (t == 0) {
                 batch_decide(DECIDE_CHECK, ra, rp, &S, &ds, len);
                 if (!S.done && a.deadline_ticks > 0 &&
@@ -389,6 +516,10 @@ __global__ __launch_bounds__(NT) void k_batch_norms(BatchDev a, int32_t maxit, d
         const int r0 = a.row_off[id], m = a.row_off[id + 1] - r0;
         const int32_t *arp = a.a_rowptr + r0;
         const int32_t *prp = a.p_rowptr + v0;
+        const int32_t *lra = a.lrA + a.lrA_off[id];
+        const int nlra = a.lrA_off[id + 1] - a.lrA_off[id];
+        const int32_t *lrp = a.lrP + a.lrP_off[id];
+        const int nlrp = a.lrP_off[id + 1] - a.lrP_off[id];
         double *v = a.xbar + v0, *z = a.xt + v0, *w = a.ybar + r0;
         double lam = 0.0;
         // ||A||_2: Rayleigh quotient of A'A
@@ -399,10 +530,22 @@ __global__ __launch_bounds__(NT) void k_batch_norms(BatchDev a, int32_t maxit, d
             for (int it = 1; it <= maxit; ++it) {
                 double acc[2] = {0.0, 0.0};
                 for (int i = t; i < m; i += NT) {
-                    double s = 0.0;
-                    for (int e = arp[i]; e < arp[i + 1]; ++e) s = s + a.a_val[e] * v[a.a_col[e]];
-                    w[i] = s;
-                    acc[0] += s * s;
+                    if (arp[i + 1] - arp[i] > LONG_ROW) continue;
+                    double sacc = 0.0;
+                    for (int e = arp[i]; e < arp[i + 1]; ++e) sacc = sacc + a.a_val[e] * v[a.a_col[e]];
+                    w[i] = sacc;
+                    acc[0] += sacc * sacc;
+                }
+                for (int qq = 0; qq < nlra; ++qq) {
+                    const int i = lra[qq];
+                    double sv[1] = {0.0};
+                    for (int e = arp[i] + t; e < arp[i + 1]; e += NT)
+                        sv[0] = sv[0] + a.a_val[e] * v[a.a_col[e]];
+                    team_sum<NT, 1>(sv, red);
+                    if (t == 0) {
+                        w[i] = sv[0];
+                        acc[0] += sv[0] * sv[0];
+                    }
                 }
                 team_reduce<NT>(acc, 1, 0, red);
                 if (t == 0) s_val[0] = acc[0];
@@ -410,13 +553,27 @@ __global__ __launch_bounds__(NT) void k_batch_norms(BatchDev a, int32_t maxit, d
                 lam = s_val[0];
                 acc[0] = 0.0;
                 for (int j = t; j < n; j += NT) {
-                    double s = 0.0;
+                    if (prp[j + 1] - prp[j] > LONG_ROW) continue;
+                    double sacc = 0.0;
                     for (int e = prp[j]; e < prp[j + 1]; ++e) {
                         const int cc = a.p_col[e];
-                        if (cc >= n) s = s + (-1.0) * (a.p_val[e] * w[cc - n]);
+                        if (cc >= n) sacc = sacc + (-1.0) * (a.p_val[e] * w[cc - n]);
                     }
-                    z[j] = s;
-                    acc[0] += s * s;
+                    z[j] = sacc;
+                    acc[0] += sacc * sacc;
+                }
+                for (int qq = 0; qq < nlrp; ++qq) {
+                    const int j = lrp[qq];
+                    double sv[1] = {0.0};
+                    for (int e = prp[j] + t; e < prp[j + 1]; e += NT) {
+                        const int cc = a.p_col[e];
+                        if (cc >= n) sv[0] = sv[0] + (-1.0) * (a.p_val[e] * w[cc - n]);
+                    }
+                    team_sum<NT, 1>(sv, red);
+                    if (t == 0) {
+                        z[j] = sv[0];
+                        acc[0] += sv[0] * sv[0];
+                    }
                 }
                 team_reduce<NT>(acc, 1, 0, red);
                 if (t == 0) s_val[1] = sqrt(acc[0]);
@@ -438,14 +595,28 @@ __global__ __launch_bounds__(NT) void k_batch_norms(BatchDev a, int32_t maxit, d
         for (int it = 1; it <= maxit; ++it) {
             double acc[2] = {0.0, 0.0};
             for (int j = t; j < n; j += NT) {
-                double s = 0.0;
+                if (prp[j + 1] - prp[j] > LONG_ROW) continue;
+                double sacc = 0.0;
                 for (int e = prp[j]; e < prp[j + 1]; ++e) {
                     const int cc = a.p_col[e];
-                    if (cc < n) s = s + a.p_val[e] * v[cc];
+                    if (cc < n) sacc = sacc + a.p_val[e] * v[cc];
                 }
-                z[j] = s;
-                acc[0] += v[j] * s;
-                acc[1] += s * s;
+                z[j] = sacc;
+            }
+            for (int qq = 0; qq < nlrp; ++qq) {
+                const int j = lrp[qq];
+                double sv[1] = {0.0};
+                for (int e = prp[j] + t; e < prp[j + 1]; e += NT) {
+                    const int cc = a.p_col[e];
+                    if (cc < n) sv[0] = sv[0] + a.p_val[e] * v[cc];
+                }
+                team_sum<NT, 1>(sv, red);
+                if (t == 0) z[j] = sv[0];
+            }
+            __syncthreads();
+            for (int j = t; j < n; j += NT) {
+                acc[0] += v[j] * z[j];
+                acc[1] += z[j] * z[j];
             }
             team_reduce<NT>(acc, 2, 0, red);
             if (t == 0) {
@@ -488,6 +659,7 @@ struct BatchData {
     DevMem var_off_d, row_off_d, a_rowptr, a_col, a_val, p_rowptr, p_col, p_val;
     DevMem c, b, l, u, rt, normA_d, normQ_d, b_inf_d, c_inf_d, omega0_d, has_x0, has_y0, x0, y0;
     DevMem x, xbar, xt, xmd0, xmd1, xrs, y, ybar, yrs, x_out, y_out, res, order_d, head, clock0;
+    DevMem lrA_off, lrA, lrP_off, lrP;  // long-row lists (rows > LONG_ROW nonzeros)
     std::vector<int32_t> order_off;  // offsets of each class in order_d
     std::vector<double> h_omega;     // staging of per-solve scalars (outlive async copies)
     std::vector<uint8_t> h_hx, h_hy;
@@ -543,6 +715,10 @@ static BatchDev make_dev(BatchData *bd) {
     a.res = bd->res.as<State>();
     a.head = bd->head.as<int32_t>();
     a.clock0 = bd->clock0.as<int64_t>();
+    a.lrA_off = bd->lrA_off.as<int32_t>();
+    a.lrA = bd->lrA.as<int32_t>();
+    a.lrP_off = bd->lrP_off.as<int32_t>();
+    a.lrP = bd->lrP.as<int32_t>();
     return a;
 }
 
@@ -573,8 +749,15 @@ static void launch_class(BatchData *bd, BatchDev a, const DevSettings &ds, int n
                                bd->normA_d.as<double>(), bd->normQ_d.as<double>());              \
         } else {                                                                                 \
             const size_t lds = (size_t)a.lds_doubles * 8;                                        \
-            int g = persistent_grid(k_batch<NT>, NT, a.order_count, bd->num_cu, lds);            \
-            hipLaunchKernelGGL(k_batch<NT>, dim3(g), dim3(NT), lds, s, a, ds);                   \
+            if (lds > 64 * 1024 &&                                                               \
+                hipFuncSetAttribute((const void *)k_batch<NT>,                                   \
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,                  \
+                                    (int)lds) != hipSuccess) {                                   \
+                a.lds_doubles = 0; /* larger LDS refused: gathered vectors stay in HBM */        \
+            }                                                                                    \
+            const size_t lds_use = (size_t)a.lds_doubles * 8;                                    \
+            int g = persistent_grid(k_batch<NT>, NT, a.order_count, bd->num_cu, lds_use);        \
+            hipLaunchKernelGGL(k_batch<NT>, dim3(g), dim3(NT), lds_use, s, a, ds);               \
         }                                                                                        \
     } while (0)
     switch (nt) {
@@ -600,6 +783,7 @@ static DevSettings batch_settings(const qp_settings *s) {
     ds.restart_mode = s->restart_mode;
     ds.fixed_K = s->fixed_K;
     ds.interval = s->restart_mode == QP_RESTART_FIXED_K ? s->fixed_K : s->check_every;
+    ds.momentum = s->momentum;
     return ds;
 }
 
@@ -746,6 +930,23 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
                 }
         }
     }
+    // rows longer than LONG_ROW nonzeros, per instance (local row ids)
+    std::vector<int32_t> lao(B + 1, 0), la, lpo(B + 1, 0), lp;
+    for (int i = 0; i < B; ++i) {
+        for (int64_t r = bd->row_off[i]; r < bd->row_off[i + 1]; ++r)
+            if (ar[r + 1] - ar[r] > LONG_ROW) la.push_back((int32_t)(r - bd->row_off[i]));
+        for (int64_t j = bd->var_off[i]; j < bd->var_off[i + 1]; ++j)
+            if (pr[j + 1] - pr[j] > LONG_ROW) lp.push_back((int32_t)(j - bd->var_off[i]));
+        lao[i + 1] = (int32_t)la.size();
+        lpo[i + 1] = (int32_t)lp.size();
+    }
+    if ((rc = bd->lrA_off.upload(lao.data(), lao.size() * 4)) ||
+        (rc = bd->lrA.upload(la.data(), la.size() * 4)) ||
+        (rc = bd->lrP_off.upload(lpo.data(), lpo.size() * 4)) ||
+        (rc = bd->lrP.upload(lp.data(), lp.size() * 4))) {
+        delete bd;
+        return rc;
+    }
     std::vector<int32_t> vo(B + 1), ro(B + 1);
     for (int i = 0; i <= B; ++i) {
         vo[i] = (int32_t)bd->var_off[i];
@@ -811,7 +1012,7 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
         // dynamic LDS per class: the largest 3 n_i + m_i that fits the cap
         int max_lds = 65536;
         (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        const int cap = std::min(max_lds, 64 * 1024) - 4096;  // room for the static LDS
+        const int cap = std::min(max_lds, 160 * 1024) - 4096;  // room for the static LDS
         for (int k = 0; k < NCLASS; ++k) {
             int64_t need = 0;
             for (int32_t id : bd->order[k]) {

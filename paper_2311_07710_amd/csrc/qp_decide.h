@@ -18,9 +18,18 @@ __device__ __forceinline__ double pdqp_cap(const DevSettings &s, double omega, i
 }
 
 // primal step p and dual step d at inner index k; *s_last carries the scale of
-// index k-1 of the same cycle (Sec. 6: min{(1 + 1/k) eta_{k-1}, cap_k}).
+// index k-1 of the same cycle (Sec. 6: min{(1 + 1/k) eta_{k-1}, cap_k}).  Plain PDHG
+// (momentum off) keeps the cap of beta = 1, i.e. (k+2) replaced by 2, for every k.
 __device__ __forceinline__ void step_at(const DevSettings &s, double omega, int64_t k,
                                         double *s_last, double *p, double *d) {
+    if (!s.momentum) {
+        const double qw = s.norm_Q / omega;
+        const double sk = s.step_safety * 2.0 / (qw + sqrt(4.0 * s.norm_A * s.norm_A + qw * qw));
+        *s_last = sk;
+        *p = sk / omega;
+        *d = sk * omega;
+        return;
+    }
     if (s.restart_mode == MODE_FIXED_K) {  // Theorem 1 / eq. (param-choice)
         const double Kf = (double)s.fixed_K;
         *p = (double)(k + 1) / (2.0 * (s.norm_Q + Kf * s.norm_A));
@@ -41,6 +50,11 @@ __device__ __forceinline__ void step_at(const DevSettings &s, double omega, int6
     *d = sk * omega;
 }
 
+// Scalars of inner iteration kj.  w is the weight of the new iterate in the running
+// average z-bar; theta_next and w_next (the weight of x in x_md) belong to iteration
+// kj+1.  Algorithm 1: w = 1/beta_k, theta_{k+1} = (k+1)/(k+2), w_next = 1/beta_{k+1}.
+// Plain PDHG: beta = theta = 1 (x_md = x, x~ = 2x - x_prev) and z-bar is the uniform
+// average of the cycle, w = 1/(k+1).
 __device__ __forceinline__ Step make_step(const DevSettings &s, double omega, int64_t kj,
                                           double *s_last) {
     double p, d;
@@ -48,9 +62,15 @@ __device__ __forceinline__ Step make_step(const DevSettings &s, double omega, in
     Step e;
     e.p = p;
     e.d = d;
-    e.w = 2.0 / (double)(kj + 2);                          // 1/beta_k
-    e.theta_next = (double)(kj + 1) / (double)(kj + 2);    // theta_{k+1}
-    e.w_next = 2.0 / (double)(kj + 3);                     // 1/beta_{k+1}
+    if (s.momentum) {
+        e.w = 2.0 / (double)(kj + 2);
+        e.theta_next = (double)(kj + 1) / (double)(kj + 2);
+        e.w_next = 2.0 / (double)(kj + 3);
+    } else {
+        e.w = 1.0 / (double)(kj + 1);
+        e.theta_next = 1.0;
+        e.w_next = 1.0;
+    }
     e.pad[0] = e.pad[1] = e.pad[2] = 0.0;
     return e;
 }

@@ -60,10 +60,14 @@ struct DevMem {
         }
         return QP_OK;
     }
+    // Copies b bytes from the host and appends UPLOAD_PAD zero bytes: kernels that
+    // read one entry past a range (an empty block at the end of an array) stay in bounds.
+    static constexpr size_t UPLOAD_PAD = 16;
     int upload(const void *src, size_t b) {
-        int rc = alloc(b < 8 ? 8 : b);
+        int rc = alloc(b + UPLOAD_PAD);
         if (rc) return rc;
         if (b) HIPCHK(hipMemcpy(p, src, b, hipMemcpyHostToDevice));
+        HIPCHK(hipMemset((char *)p + b, 0, UPLOAD_PAD));
         return QP_OK;
     }
     template <class T> T *as() const { return (T *)p; }

@@ -62,6 +62,7 @@ struct Panels {
 };
 
 constexpr int PANEL_ROWS = 1024;  // rows per panel block
+constexpr int FOLD_SLOTS = 64;    // spare partial slots for the two-stage KKT reduction
 
 struct Csr {
     const int32_t *rowptr;
@@ -103,6 +104,7 @@ struct DevSettings {
     double step_safety, norm_A, norm_Q, b_inf, c_inf;
     int64_t max_iter;
     int32_t restart_mode, fixed_K, interval;
+    int32_t momentum;  // 1: Algorithm 1 weights; 0: plain PDHG (beta = theta = 1)
 };
 
 enum : int { DECIDE_INIT = 0, DECIDE_CHECK = 1, DECIDE_FALLBACK = 2 };
@@ -118,6 +120,27 @@ struct Vecs {
     const uint8_t *rt;
 };
 
+// ---- diagonal preconditioning (qp_scale.hip) ----
+enum : int { SCALE_MAX = 0, SCALE_L2 = 1, SCALE_SUM = 2 };
+struct ScaleInput {
+    int64_t n, m;                       // variables / constraint rows (all instances)
+    const int32_t *a_rowptr, *a_col;    // device CSR of A (batch: local columns)
+    double *a_val;                      // scaled in place
+    const int32_t *p_rowptr, *p_col;    // device CSR of P = [Q | -A']
+    double *p_val;                      // scaled in place
+    const int64_t *var_off, *row_off;   // device batch offsets [count+1], or nullptr
+    int32_t count;
+    int32_t ruiz_iters, l2, pc;
+};
+// d (device, n+m): receives the cumulative scaling (D2 for variables, then D1);
+// work: 2(n+m) doubles.
+int precondition_device(hipStream_t s, const ScaleInput &in, double *work, double *d);
+void launch_gather_values(hipStream_t s, double *dst, const double *src, const int32_t *idx,
+                          int64_t len);
+// out = in * d (divide = 0) or in / d (divide = 1), elementwise
+void launch_scale_pair(hipStream_t s, double *out, const double *in, const double *d,
+                       int64_t len, int divide);
+
 // ---- launchers (qp_kernels.hip) ----
 void launch_dual(hipStream_t s, const Blocks &bk, const Csr &A, const Vecs &v, const Step *step,
                  const State *st);
@@ -127,9 +150,8 @@ void launch_kkt_rows(hipStream_t s, const Blocks &bk, const Csr &A, const Vecs &
                      double *partials, const State *st);
 void launch_kkt_cols(hipStream_t s, const Blocks &bk, const Csr &P, const Vecs &v,
                      double *partials, const State *st, int64_t n);
-void launch_decide(hipStream_t s, int mode, const double *partA, int32_t nslotA,
-                   const double *partP, int32_t nslotP, State *st, Step *table,
-                   const DevSettings &ds, int32_t len);
+void launch_decide(hipStream_t s, int mode, double *partA, int32_t nslotA, double *partP,
+                   int32_t nslotP, State *st, Step *table, const DevSettings &ds, int32_t len);
 void launch_apply(hipStream_t s, const Vecs &v, int md_out, const State *st, int64_t n,
                   int64_t m);
 void launch_init(hipStream_t s, const Vecs &v, const double *x0, const double *y0, int64_t n,

@@ -121,6 +121,24 @@ __device__ __forceinline__ void dual_epilogue(int i, double v, double *__restric
     y[i] = yn;
 }
 
+// Streams the (column, value) pairs of entries e0 + i*BS + t, i < EPT, of a block with
+// every load issued before any result is used, so that the gathers that follow are all
+// in flight together.  Lanes past the block's end read entry e0 (device arrays carry a
+// zero pad entry, so e0 is readable even for an empty block at the end of an array) and
+// get value 0: their products are zero and never summed.
+__device__ __forceinline__ void load_block(const int32_t *__restrict__ col,
+                                           const double *__restrict__ val, int e0, int e1,
+                                           int t, int (&cols)[EPT], double (&vals)[EPT]) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = e0 + i * BS + t;
+        const int ee = e < e1 ? e : e0;
+        cols[i] = __builtin_nontemporal_load(&col[ee]);
+        const double v = __builtin_nontemporal_load(&val[ee]);
+        vals[i] = e < e1 ? v : 0.0;
+    }
+}
+
 __global__ __launch_bounds__(BS) void k_dual(Blocks bk, Csr A, const double *__restrict__ xt,
                                              double *__restrict__ y, double *__restrict__ ybar,
                                              const double *__restrict__ b,
@@ -135,19 +153,12 @@ __global__ __launch_bounds__(BS) void k_dual(Blocks bk, Csr A, const double *__r
     const int t = threadIdx.x;
     int cols[EPT];
     double vals[EPT];
+    load_block(A.col, A.val, B.e0, B.e1, t, cols, vals);
+    double g[EPT];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int e = B.e0 + i * BS + t;
-        if (e < B.e1) {
-            cols[i] = __builtin_nontemporal_load(&A.col[e]);
-            vals[i] = __builtin_nontemporal_load(&A.val[e]);
-        }
-    }
+    for (int i = 0; i < EPT; ++i) g[i] = xt[cols[i]];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int e = B.e0 + i * BS + t;
-        if (e < B.e1) prod[i * BS + t] = vals[i] * xt[cols[i]];
-    }
+    for (int i = 0; i < EPT; ++i) prod[i * BS + t] = vals[i] * g[i];
     __syncthreads();
     const double d = step->d, w = step->w;
     const int lr = bk.lr[bi];
@@ -206,23 +217,15 @@ __global__ __launch_bounds__(BS) void k_primal(Blocks bk, Csr P, PrimalArgs a,
     const int t = threadIdx.x;
     int cols[EPT];
     double vals[EPT];
+    load_block(P.col, P.val, B.e0, B.e1, t, cols, vals);
+    double g[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-        const int e = B.e0 + i * BS + t;
-        if (e < B.e1) {
-            cols[i] = __builtin_nontemporal_load(&P.col[e]);
-            vals[i] = __builtin_nontemporal_load(&P.val[e]);
-        }
+        const int cc = cols[i];
+        g[i] = *(cc < n ? a.xmd_in + cc : a.y + (cc - n));
     }
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int e = B.e0 + i * BS + t;
-        if (e < B.e1) {
-            const int cc = cols[i];
-            const double v = cc < n ? a.xmd_in[cc] : a.y[cc - n];
-            prod[i * BS + t] = vals[i] * v;
-        }
-    }
+    for (int i = 0; i < EPT; ++i) prod[i * BS + t] = vals[i] * g[i];
     __syncthreads();
     const double p = step->p, w = step->w, th1 = step->theta_next, w1 = step->w_next;
     const int lr = bk.lr[bi];
@@ -304,13 +307,19 @@ __global__ __launch_bounds__(BS) void k_kkt_rows(Blocks bk, Csr A, KktRowArgs a,
     const int bi = xcd_block(blockIdx.x, gridDim.x);
     const Block B = bk.blk[bi];
     const int t = threadIdx.x;
-    for (int i = 0; i < EPT; ++i) {
-        const int e = B.e0 + i * BS + t;
-        if (e < B.e1) {
-            const int cc = A.col[e];
-            const double v = A.val[e];
-            prod0[i * BS + t] = v * a.x[cc];
-            prod1[i * BS + t] = v * a.xbar[cc];
+    {
+        int cols[EPT];
+        double vals[EPT], g0[EPT], g1[EPT];
+        load_block(A.col, A.val, B.e0, B.e1, t, cols, vals);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            g0[i] = a.x[cols[i]];
+            g1[i] = a.xbar[cols[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            prod0[i * BS + t] = vals[i] * g0[i];
+            prod1[i * BS + t] = vals[i] * g1[i];
         }
     }
     __syncthreads();
@@ -394,15 +403,22 @@ __global__ __launch_bounds__(BS) void k_kkt_cols(Blocks bk, Csr P, KktColArgs a,
     const int bi = xcd_block(blockIdx.x, gridDim.x);
     const Block B = bk.blk[bi];
     const int t = threadIdx.x;
-    for (int i = 0; i < EPT; ++i) {
-        const int e = B.e0 + i * BS + t;
-        if (e < B.e1) {
-            const int cc = P.col[e];
-            const double v = P.val[e];
+    {
+        int cols[EPT];
+        double vals[EPT], g0[EPT], g1[EPT];
+        load_block(P.col, P.val, B.e0, B.e1, t, cols, vals);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int cc = cols[i];
             const bool ya = cc >= n;
-            prod0[i * BS + t] = v * (ya ? a.y[cc - n] : a.x[cc]);
-            prod1[i * BS + t] = v * (ya ? a.ybar[cc - n] : a.xbar[cc]);
-            isA[i * BS + t] = ya;
+            g0[i] = *(ya ? a.y + (cc - n) : a.x + cc);
+            g1[i] = *(ya ? a.ybar + (cc - n) : a.xbar + cc);
+        }
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            prod0[i * BS + t] = vals[i] * g0[i];
+            prod1[i * BS + t] = vals[i] * g1[i];
+            isA[i * BS + t] = cols[i] >= n;
         }
     }
     __syncthreads();
@@ -468,6 +484,42 @@ __global__ __launch_bounds__(BS) void k_kkt_cols(Blocks bk, Csr P, KktColArgs a,
 // decision kernel (one workgroup): relKKT, candidate, restart, primal weight,
 // step table for the next interval
 // ---------------------------------------------------------------------------
+// First stage of the partial reduction: workgroup g folds the per-block KKT partials of
+// slots [g*per, min((g+1)*per, nslot)) into one slot of out (the first NMAX entries of a
+// slot are maxima, the rest sums), in a fixed order.
+template <int NV, int NMAX>
+__global__ __launch_bounds__(BS) void k_fold_slots(const double *__restrict__ part, int32_t nslot,
+                                                   int32_t per, double *__restrict__ out,
+                                                   const State *__restrict__ st) {
+    if (st->done) return;
+    __shared__ double red[NV][BS];
+    const int t = threadIdx.x;
+    const int i0 = blockIdx.x * per;
+    const int i1 = min(nslot, i0 + per);
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (int i = i0 + t; i < i1; i += BS) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double z = part[(size_t)i * NV + v];
+            acc[v] = v < NMAX ? nmax(acc[v], z) : acc[v] + z;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) red[v][t] = acc[v];
+    __syncthreads();
+    for (int h = BS / 2; h >= 1; h >>= 1) {
+        if (t < h) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                red[v][t] = v < NMAX ? nmax(red[v][t], red[v][t + h]) : red[v][t] + red[v][t + h];
+        }
+        __syncthreads();
+    }
+    if (t < NV) out[(size_t)blockIdx.x * NV + t] = red[t][0];
+}
+
 __global__ __launch_bounds__(BS) void k_decide(int mode, const double *__restrict__ partA,
                                                int32_t nslotA, const double *__restrict__ partP,
                                                int32_t nslotP, State *st, Step *table,
@@ -625,17 +677,23 @@ __global__ __launch_bounds__(BS) void k_spmv_plain(Blocks bk, Csr M, const doubl
     const int bi = xcd_block(blockIdx.x, gridDim.x);
     const Block B = bk.blk[bi];
     const int t = threadIdx.x;
-    for (int i = 0; i < EPT; ++i) {
-        const int e = B.e0 + i * BS + t;
-        if (e < B.e1) {
-            const int cc = M.col[e];
-            const double v = M.val[e];
-            double pr = 0.0;
-            if (cc < split) {
-                if (x) pr = v * x[cc];
-            } else if (x2) {
-                pr = sign2 * (v * x2[cc - split]);
-            }
+    {
+        int cols[EPT];
+        double vals[EPT], g[EPT];
+        load_block(M.col, M.val, B.e0, B.e1, t, cols, vals);
+        // a missing operand contributes zero; its entries read a valid dummy address
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int cc = cols[i];
+            const bool first = cc < split;
+            const double *src = first ? (x ? x + cc : M.val) : (x2 ? x2 + (cc - split) : M.val);
+            g[i] = *src;
+        }
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const bool first = cols[i] < split;
+            const double pr = first ? (x ? vals[i] * g[i] : 0.0)
+                                    : (x2 ? sign2 * (vals[i] * g[i]) : 0.0);
             prod[i * BS + t] = pr;
         }
     }
@@ -761,11 +819,30 @@ void launch_kkt_cols(hipStream_t s, const Blocks &bk, const Csr &P, const Vecs &
     hipLaunchKernelGGL(k_kkt_cols, dim3(bk.nblk), dim3(BS), 0, s, bk, P, a, st, (int32_t)n);
 }
 
-void launch_decide(hipStream_t s, int mode, const double *partA, int32_t nslotA,
-                   const double *partP, int32_t nslotP, State *st, Step *table,
-                   const DevSettings &ds, int32_t len) {
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(BS), 0, s, mode, partA, nslotA, partP, nslotP, st,
-                       table, ds, len);
+// The partial buffers hold FOLD_SLOTS spare slots after the nslot block partials: many
+// partials are first folded there by up to FOLD_SLOTS workgroups, so the single-workgroup
+// decision reads few.
+void launch_decide(hipStream_t s, int mode, double *partA, int32_t nslotA, double *partP,
+                   int32_t nslotP, State *st, Step *table, const DevSettings &ds, int32_t len) {
+    auto fold = [&](double *part, int32_t nslot, int nv) -> int32_t {
+        if (nslot <= 2 * BS) return 0;
+        const int32_t per = std::max<int32_t>(2 * BS, (nslot + FOLD_SLOTS - 1) / FOLD_SLOTS);
+        const int32_t g = (nslot + per - 1) / per;
+        double *out = part + (size_t)nslot * nv;
+        if (nv == RA_NV)
+            hipLaunchKernelGGL((k_fold_slots<RA_NV, 4>), dim3(g), dim3(BS), 0, s, part, nslot, per,
+                               out, st);
+        else
+            hipLaunchKernelGGL((k_fold_slots<RP_NV, 6>), dim3(g), dim3(BS), 0, s, part, nslot, per,
+                               out, st);
+        return g;
+    };
+    const int32_t gA = fold(partA, nslotA, RA_NV);
+    const int32_t gP = fold(partP, nslotP, RP_NV);
+    const double *pa = gA ? partA + (size_t)nslotA * RA_NV : partA;
+    const double *pp = gP ? partP + (size_t)nslotP * RP_NV : partP;
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(BS), 0, s, mode, pa, gA ? gA : nslotA, pp,
+                       gP ? gP : nslotP, st, table, ds, len);
 }
 
 void launch_apply(hipStream_t s, const Vecs &v, int md_out, const State *st, int64_t n,
@@ -855,23 +932,18 @@ __global__ __launch_bounds__(BS) void k_panel_spmv(Panels pn, const double *__re
     const int t = threadIdx.x;
     int cols[EPT];
     double vals[EPT];
+    load_block(pn.col, pn.val, B.e0, B.e1, t, cols, vals);
+    double g[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-        const int e = B.e0 + i * BS + t;
-        if (e < B.e1) {
-            cols[i] = __builtin_nontemporal_load(&pn.col[e]);
-            vals[i] = __builtin_nontemporal_load(&pn.val[e]);
-        }
+        const int cc = cols[i];
+        if (PHASE == 0)
+            g[i] = v1[cc];
+        else
+            g[i] = *(cc < split ? v1 + cc : v2 + (cc - split));
     }
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int e = B.e0 + i * BS + t;
-        if (e < B.e1) {
-            const int cc = cols[i];
-            const double v = cc < split ? v1[cc] : v2[cc - split];
-            prod[i * BS + t] = vals[i] * v;
-        }
-    }
+    for (int i = 0; i < EPT; ++i) prod[i * BS + t] = vals[i] * g[i];
     __syncthreads();
     const int32_t *rp = pn.rowptr + (size_t)B.panel * (size_t)(pn.R + 1);
     double *out = pn.part + (size_t)B.panel * (size_t)pn.R;

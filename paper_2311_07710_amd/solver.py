@@ -40,6 +40,7 @@ class Settings:
     device: int = 0
     panels_dual: int = 0
     panels_primal: int = 0
+    momentum: int = 1
 
     def c_struct(self) -> B.qp_settings:
         s = B.qp_settings()
@@ -205,6 +206,12 @@ class BatchSolver:
         if getattr(self, "h", None):
             self.lib.qp_free(self.h)
             self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
     __del__ = close
 

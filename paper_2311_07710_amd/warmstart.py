@@ -33,20 +33,49 @@ def targets(x, y, omega) -> np.ndarray:
     return np.hstack([x, y, np.log(np.asarray(omega))[:, None]])
 
 
-def solve_family(fam, idx, settings: Settings, x0=None, y0=None, omega0=None, threads=None):
-    """Batched solves of family members idx; returns (X [k,n], Y [k,m], results, seconds)."""
-    batch = fam.batch(idx)
-    bs = BatchSolver(batch, settings)
-    if threads is not None:
-        bs.set_threads(threads)
-    t = time.perf_counter()
-    x, y, res = bs.solve(x0=None if x0 is None else np.ascontiguousarray(x0).ravel(),
-                         y0=None if y0 is None else np.ascontiguousarray(y0).ravel(),
-                         omega0=omega0)
-    dt = time.perf_counter() - t
-    bs.close()
+def family_norms(fam, settings: Settings | None = None):
+    """||A||_2 and ||Q||_2 of the family.  A and Q are the same for every member
+    (only c and b vary), so one power iteration on member 0 serves them all."""
+    from .solver import Solver
+    with Solver(fam.instance(0), settings or Settings()) as s:
+        return s.norms()
+
+
+def solve_family(fam, idx, settings: Settings, x0=None, y0=None, omega0=None, threads=None,
+                 chunk: int = 0, log=None):
+    """Batched solves of family members idx; returns (X [k,n], Y [k,m], results, seconds).
+
+    With chunk > 0 the members are solved in launches of at most chunk instances
+    (log receives one line per launch).  Unless settings carries norm overrides,
+    the family's norms are computed once and passed to every launch."""
+    import dataclasses
+    idx = np.asarray(idx)
+    if settings.norm_A <= 0.0 or settings.norm_Q <= 0.0:
+        nA, nQ = family_norms(fam, settings)
+        settings = dataclasses.replace(settings, norm_A=nA, norm_Q=nQ)
     n, m = fam.base.n, fam.base.m
-    return x.reshape(len(idx), n), y.reshape(len(idx), m), res, dt
+    k = len(idx)
+    step = k if chunk <= 0 else chunk
+    X, Y, res, dt = np.zeros((k, n)), np.zeros((k, m)), [], 0.0
+    for s0 in range(0, k, step):
+        sl = slice(s0, min(k, s0 + step))
+        bs = BatchSolver(fam.batch(idx[sl]), settings)
+        if threads is not None:
+            bs.set_threads(threads)
+        t = time.perf_counter()
+        x, y, r = bs.solve(x0=None if x0 is None else np.ascontiguousarray(x0[sl]).ravel(),
+                           y0=None if y0 is None else np.ascontiguousarray(y0[sl]).ravel(),
+                           omega0=None if omega0 is None else np.asarray(omega0)[sl])
+        dt += time.perf_counter() - t
+        bs.close()
+        cnt = sl.stop - sl.start
+        X[sl] = x.reshape(cnt, n)
+        Y[sl] = y.reshape(cnt, m)
+        res.extend(r)
+        if log:
+            its = sum(q["iterations"] for q in r)
+            log(f"solved {sl.stop}/{k} (chunk {cnt}, {its} iterations, {dt:.2f} s total)")
+    return X, Y, res, dt
 
 
 @dataclass
@@ -60,8 +89,9 @@ class WarmStartModel:
     m: int
     history: list
 
-    def predict(self, F: np.ndarray, batch: int = 256):
+    def predict(self, F: np.ndarray, batch: int = 0):
         import torch
+        batch = self.mlp.max_batch if batch <= 0 else min(batch, self.mlp.max_batch)
         Z = ((F - self.f_mean) / self.f_std).astype(np.float32)
         outs = []
         for s in range(0, Z.shape[0], batch):

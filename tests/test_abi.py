@@ -116,7 +116,8 @@ def test_malformed_input_rejected_on_host(mutate, needle):
 @pytest.mark.parametrize("kw,needle", [({"check_every": 0}, "check_every"),
                                        ({"restart_mode": 9}, "restart_mode"),
                                        ({"restart_mode": 1, "fixed_K": 0}, "fixed_K"),
-                                       ({"eps": -1.0}, "eps")])
+                                       ({"eps": -1.0}, "eps"),
+                                       ({"momentum": 2}, "momentum")])
 def test_bad_settings_rejected(kw, needle):
     rc, msg = _create_rc(_tiny(), **kw)
     assert rc == B.QP_ERR_INVALID_ARGUMENT and needle in msg

@@ -37,15 +37,37 @@ def _mixed_batch():
     G = rng.standard_normal((n, n))
     insts.append(qp_refs.make_qp(G @ G.T / n + np.eye(n), np.zeros((0, n)), rng.standard_normal(n),
                                  [], np.full(n, -1.0), np.full(n, 1.0), []))
+    insts.append(_long_row_instance())
     return insts
 
 
-def _oracle_all(orc, insts, eps, max_iter=200000, x0s=None, y0s=None, fb=1):
+def _long_row_instance(seed=11, n=300, m=160):
+    """Rows of A and of P = [Q | -A'] longer than one team pass: Q = diag + v v'
+    is dense, A has one dense row and one dense column, the rest is sparse."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(n)
+    Q = np.diag(rng.uniform(0.5, 2.0, n)) + np.outer(v, v) / n
+    A = np.zeros((m, n))
+    for i in range(m):
+        A[i, rng.choice(n, 5, replace=False)] = rng.standard_normal(5)
+    A[0, :] = rng.standard_normal(n)
+    A[:, 0] = rng.standard_normal(m)
+    l, u = np.full(n, -2.0), np.full(n, 2.0)
+    xf = rng.uniform(-1.0, 1.0, n)
+    row_type = np.where(np.arange(m) % 3 == 0, qpgen.instances.EQ, qpgen.instances.GE)
+    ax = A @ xf                                      # xf is strictly feasible for GE rows
+    b = np.where(row_type == qpgen.instances.EQ, ax, ax - rng.uniform(0.0, 1.0, m))
+    return qp_refs.make_qp(Q, A, rng.standard_normal(n), b, l, u, row_type, name="long_rows")
+
+
+def _oracle_all(orc, insts, eps, max_iter=200000, x0s=None, y0s=None, fb=1, momentum=1,
+                restart_mode=0):
     out = []
     for i, qp in enumerate(insts):
         nA, _ = orc.norm_A(qp, 1000, 1e-7)
         nQ, _ = orc.norm_Q(qp, 1000, 1e-7)
-        s = orc.OracleSettings(eps=eps, max_iter=max_iter, norm_A=nA, norm_Q=nQ, warm_fallback=fb)
+        s = orc.OracleSettings(eps=eps, max_iter=max_iter, norm_A=nA, norm_Q=nQ, warm_fallback=fb,
+                               momentum=momentum, restart_mode=restart_mode)
         x, y, r, _ = orc.solve(qp, s, x0=None if x0s is None else x0s[i],
                                y0=None if y0s is None else y0s[i])
         out.append((x, y, r, nA, nQ))
@@ -78,6 +100,19 @@ def test_batch_matches_oracle_per_instance(orc, qpa):
     with_norms.set_norms([r[3] for r in ref], [r[4] for r in ref])
     xg, yg, rg = with_norms.solve()
     with_norms.close()
+    _compare(batch, xg, yg, rg, ref)
+
+
+@pytest.mark.parametrize("restart_mode", [0, 2])
+def test_batch_plain_pdhg(orc, qpa, restart_mode):
+    """Sec. 5 baseline (no momentum) in the persistent kernel, long rows included."""
+    insts = _mixed_batch()[:5] + [_long_row_instance()]
+    batch = qpgen.concat_batch(insts)
+    ref = _oracle_all(orc, insts, eps=1e-6, momentum=0, restart_mode=restart_mode)
+    bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6, momentum=0, restart_mode=restart_mode))
+    bs.set_norms([r[3] for r in ref], [r[4] for r in ref])
+    xg, yg, rg = bs.solve()
+    bs.close()
     _compare(batch, xg, yg, rg, ref)
 
 

@@ -43,16 +43,16 @@ def _norms(orc, qp):
 
 def _pair(orc, qpa, qp, *, eps=1e-6, max_iter=200000, check_every=64, mode=0, fixed_K=100,
           x0=None, y0=None, omega0=0.0, warm_fallback=1, use_graph=1, norms=None, log=True,
-          panels=(0, 0)):
+          panels=(0, 0), momentum=1):
     nA, nQ = norms if norms is not None else _norms(orc, qp)
     os_ = orc.OracleSettings(eps=eps, max_iter=max_iter, check_every=check_every,
                              restart_mode=mode, fixed_K=fixed_K, norm_A=nA, norm_Q=nQ,
-                             warm_fallback=warm_fallback)
+                             warm_fallback=warm_fallback, momentum=momentum)
     xo, yo, ro, lo = orc.solve(qp, os_, x0=x0, y0=y0, omega0=omega0, log_cap=100000)
     gs = qpa.Settings(eps=eps, max_iter=max_iter, check_every=check_every, restart_mode=mode,
                       fixed_K=fixed_K, norm_A=nA, norm_Q=nQ, warm_fallback=warm_fallback,
                       use_graph=use_graph, log_checks=1 if log else 0,
-                      panels_dual=panels[0], panels_primal=panels[1])
+                      panels_dual=panels[0], panels_primal=panels[1], momentum=momentum)
     with qpa.Solver(qp, gs) as s:
         xg, yg, rg = s.solve(x0=x0, y0=y0, omega0=omega0)
         lg = s.check_log()
@@ -197,6 +197,24 @@ def test_restart_modes(orc, qpa, mode, kw):
     args = dict(eps=1e-6)
     args.update(kw)
     o, g = _pair(orc, qpa, qp, mode=mode, **args)
+    _assert_parity(orc, qp, o, g)
+
+
+# Sec. 5 baselines: plain PDHG (no momentum) under every restart rule
+@pytest.mark.parametrize("mode,kw", [(0, {}), (1, {"fixed_K": 100}), (2, {}),
+                                     (3, {"eps": 1e-4, "max_iter": 6000})])
+def test_pdhg_modes(orc, qpa, mode, kw):
+    qp = qpgen.tiny_random_qp(2)
+    args = dict(eps=1e-6)
+    args.update(kw)
+    o, g = _pair(orc, qpa, qp, mode=mode, momentum=0, **args)
+    _assert_parity(orc, qp, o, g)
+
+
+@pytest.mark.parametrize("panels", [(1, 1), (4, 4)])
+def test_pdhg_scaled_fixed_iterations(orc, qpa, panels):
+    qp = qpgen.large_random_qp(seed=2, n=30000, m=15000)
+    o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=300, momentum=0, panels=panels)
     _assert_parity(orc, qp, o, g)
 
 

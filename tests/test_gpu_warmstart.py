@@ -29,7 +29,13 @@ def test_learned_warm_start_gain(ws):
     fam = qpgen.portfolio_family(seed=5, n_assets=400, k=20, count=1400)
     n, m = fam.base.n, fam.base.m
     tr, te = np.arange(1200), np.arange(1200, 1400)
-    X, Y, res, t_lab = ws.solve_family(fam, tr, Settings(eps=1e-8))
+    nA, nQ = ws.family_norms(fam)
+    with ws.BatchSolver(fam.batch(np.arange(3)), Settings()) as b:
+        a3, q3 = b.norms()
+    # the family shares A and Q: batched power iteration agrees with the single one
+    assert np.allclose(a3, nA, rtol=1e-3) and np.allclose(q3, nQ, rtol=1e-3)
+    X, Y, res, t_lab = ws.solve_family(fam, tr, Settings(eps=1e-8), chunk=512,
+                                       log=lambda s: print(s, flush=True))
     assert all(r["status"] == 0 for r in res)
     omega = np.array([r["omega"] for r in res])
     model = ws.train(ws.features(fam, tr), ws.targets(X, Y, omega), n, m, hidden=(256, 256),

@@ -528,3 +528,115 @@ def test_iteration_limit_and_numerical_error(orc):
     bad.c[3] = np.nan
     _, _, r2, _ = orc.solve(bad, orc.OracleSettings(norm_A=6.0, norm_Q=24.0))
     assert r2["status"] == orc.NUMERICAL_ERROR
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5 baselines: PDHG without momentum (beta = theta = 1), with and without restart
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nA,nQ,omega", [(6.2, 24.4, 8.5), (1.0, 0.0, 1.0), (3.0, 100.0, 0.01)])
+def test_pdhg_constant_step_condition(orc, nA, nQ, omega):
+    """Plain PDHG: the step condition of Lemma 2 with beta = 1 (1/eta - ||Q|| - ||A||^2 tau >= 0)
+    holds with equality without the 0.99 factor, and the step is the same at every k."""
+    s = orc.OracleSettings(momentum=0)
+    p, d, sc = orc.step_schedule(s, nA, nQ, omega, 50)
+    assert np.all(p == p[0]) and np.all(d == d[0])
+    np.testing.assert_allclose(p, sc / omega, rtol=1e-15)
+    np.testing.assert_allclose(d, sc * omega, rtol=1e-15)
+    assert 1.0 / p[0] - nQ - nA**2 * d[0] > 0.0
+    p1, d1, _ = orc.step_schedule(orc.OracleSettings(momentum=0, step_safety=1.0), nA, nQ, omega, 1)
+    assert 1.0 / p1[0] - nQ - nA**2 * d1[0] == pytest.approx(0.0, abs=1e-9 / p1[0])
+    # the fixed-K restart mode does not switch plain PDHG to the Theorem 1 schedule
+    pk, dk, _ = orc.step_schedule(orc.OracleSettings(momentum=0, restart_mode=orc.RESTART_FIXED_K,
+                                                     fixed_K=10), nA, nQ, omega, 10)
+    np.testing.assert_array_equal(pk, p[:10])
+    np.testing.assert_array_equal(dk, d[:10])
+
+
+def test_pdhg_uniform_average(orc):
+    """Without momentum z-bar is the plain mean of the cycle's iterates z^1..z^K."""
+    qp = qpgen.tiny_random_qp(2)
+    s = orc.OracleSettings(momentum=0)
+    nA, nQ, omega = 6.5, 25.0, 1.3
+    K = 12
+    xs, ys = [], []
+    for i in range(1, K + 1):
+        x, y, _, _ = orc.run_inner(qp, s, nA, nQ, omega, i)
+        xs.append(x); ys.append(y)
+    _, _, xb, yb = orc.run_inner(qp, s, nA, nQ, omega, K)
+    np.testing.assert_allclose(xb, np.mean(xs, axis=0), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(yb, np.mean(ys, axis=0), rtol=1e-12, atol=1e-13)
+
+
+def test_pdhg_without_rows_is_projected_gradient(orc):
+    """m = 0: PDHG without momentum is projected gradient descent x+ = clip(x - eta (Qx + c))
+    with the constant step; the accelerated variant is not (it evaluates Q at x_md)."""
+    rng = np.random.default_rng(21)
+    n = 9
+    G = rng.standard_normal((n, n))
+    Q = G @ G.T / n + np.eye(n)
+    c = rng.standard_normal(n)
+    l, u = np.full(n, -0.3), np.full(n, 0.4)
+    qp = qp_refs.make_qp(Q, np.zeros((0, n)), c, [], l, u, [])
+    nQ = float(np.linalg.eigvalsh(Q).max())
+    s = orc.OracleSettings(momentum=0)
+    p, _, _ = orc.step_schedule(s, 0.0, nQ, 1.0, 1)
+    x = np.zeros(n)
+    for _ in range(25):
+        x = np.clip(x - p[0] * (Q @ x + c), l, u)
+    xg, _, _, _ = orc.run_inner(qp, s, 0.0, nQ, 1.0, 25)
+    np.testing.assert_allclose(xg, x, rtol=1e-12, atol=1e-14)
+    xa, _, _, _ = orc.run_inner(qp, orc.OracleSettings(), 0.0, nQ, 1.0, 25)
+    assert np.max(np.abs(xa - x)) > 1e-6
+
+
+def test_pdhg_second_iteration_by_hand(orc):
+    """theta = 1 and beta = 1: the second dual step extrapolates to 2 x^1 - x^0 and the
+    second primal step applies Q at x^1 itself."""
+    qp = qpgen.tiny_random_qp(1)
+    Q, A = qp.dense()
+    nA, nQ, omega = 6.0, 24.0, 2.0
+    s = orc.OracleSettings(momentum=0)
+    p, d, _ = orc.step_schedule(s, nA, nQ, omega, 2)
+    x1, y1, _, _ = orc.run_inner(qp, s, nA, nQ, omega, 1)
+    ge = qp.row_type == 1
+    y2 = y1 - d[1] * (A @ (2.0 * x1) - qp.b)
+    y2[ge] = np.maximum(y2[ge], 0.0)
+    x2 = np.clip(x1 - p[1] * (Q @ x1 + qp.c - A.T @ y2), qp.l, qp.u)
+    x, y, xb, yb = orc.run_inner(qp, s, nA, nQ, omega, 2)
+    np.testing.assert_allclose(y, y2, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(x, x2, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(xb, 0.5 * (x1 + x2), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_restarted_pdhg_reaches_bruteforce_kkt(orc, seed):
+    qp = qp_refs.random_tiny_qp(seed, n=5, m=3)
+    best = qp_refs.brute_force_kkt(qp)
+    assert best is not None
+    f_star, x_star, _ = best
+    for mode in (orc.RESTART_ADAPTIVE, orc.RESTART_HALVING):
+        x, y, r, _ = orc.solve(qp, orc.OracleSettings(eps=1e-10, max_iter=400000, momentum=0,
+                                                      restart_mode=mode))
+        assert r["status"] == orc.OPTIMAL, r
+        assert r["primal_obj"] == pytest.approx(f_star, rel=1e-7, abs=1e-7)
+        np.testing.assert_allclose(x, x_star, rtol=1e-5, atol=1e-6)
+
+
+def test_momentum_and_restart_cut_iterations(orc):
+    """Sec. 5's ablation on the tiny random class: under the same restart rule the
+    accelerated method needs fewer iterations than plain PDHG (shifted geometric mean,
+    shift 10, as in the paper's tables), and restarts help plain PDHG too."""
+    def sgm(v):
+        return math.exp(np.mean(np.log(np.asarray(v, float) + 10.0))) - 10.0
+    its = {}
+    for name, mom, mode in (("rAPDHG", 1, orc.RESTART_ADAPTIVE),
+                            ("rPDHG", 0, orc.RESTART_ADAPTIVE),
+                            ("rAPDHG-halving", 1, orc.RESTART_HALVING),
+                            ("rPDHG-halving", 0, orc.RESTART_HALVING),
+                            ("PDHG", 0, orc.RESTART_NONE)):
+        its[name] = sgm([orc.solve(qpgen.tiny_random_qp(seed),
+                                   orc.OracleSettings(eps=1e-6, max_iter=50000, momentum=mom,
+                                                      restart_mode=mode))[2]["iterations"]
+                         for seed in range(1, 9)])
+    assert its["rAPDHG"] < its["rPDHG"] < its["PDHG"]
+    assert its["rAPDHG-halving"] < its["rPDHG-halving"] < its["PDHG"]
