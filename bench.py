@@ -48,6 +48,8 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="time with graph replay instead of per-kernel hipEvents")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched MPC section")
+    ap.add_argument("--no-classes", action="store_true",
+                    help="skip the seven synthetic classes at medium size")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the Sec. 5 momentum/restart ablation")
     ap.add_argument("--no-warmstart", action="store_true",
@@ -191,6 +193,8 @@ def main():
     solver.close()
     if not args.no_batch:
         out["batched_mpc"] = bench_batch(log)
+    if not args.no_classes:
+        out["classes"] = bench_classes(log)
     if not args.no_ablation:
         out["ablation"] = bench_ablation(log)
     if not args.no_warmstart:
@@ -279,6 +283,48 @@ def bench_ablation(log):
                 "solved": solved, "sgm10_iterations": sgm, "seconds": dt}
             log(f"[bench] ablation eps {eps:g}: {name}: solved {solved}/{batch.count}, "
                 f"SGM10 {sgm:.0f} iterations, {dt:.2f}s")
+    return out
+
+
+def bench_classes(log):
+    """The seven synthetic classes of the paper's large-scale set at medium size (about
+    1-4 M nonzeros each), preconditioned (Sec. 5), solved to relKKT 1e-6 one instance at
+    a time: iterations, seconds and iterations per second."""
+    import numpy as np
+    import paper_2311_07710_amd as qpa
+    import qpgen
+    makers = {
+        "random_qp": lambda: qpgen.large_random_qp(seed=12, n=150_000, m=75_000),
+        "eq_qp": lambda: qpgen.eq_qp(seed=13, n=200_000),
+        "control": lambda: qpgen.mpc_qp(np.random.default_rng(14), 2000, 20, 10,
+                                        name="control_T2000_nx20_nu10"),
+        "portfolio": lambda: qpgen.portfolio_qp(seed=15, n_assets=200_000, k=1000),
+        "huber": lambda: qpgen.huber_qp(seed=16, n_features=10_000, m_samples=100_000,
+                                        density=0.003),
+        "lasso": lambda: qpgen.lasso_qp(seed=17, n_features=10_000, m_samples=100_000,
+                                        density=0.003),
+        "svm": lambda: qpgen.svm_qp(seed=18, n_features=10_000, m_samples=100_000,
+                                    density=0.003),
+    }
+    out = {}
+    for name, make in makers.items():
+        t = time.time()
+        qp = make()
+        gen_s = time.time() - t
+        t = time.time()
+        with qpa.Solver(qp, qpa.Settings(eps=1e-6, precondition=1, time_limit_s=60.0)) as s:
+            create_s = time.time() - t
+            t = time.perf_counter()
+            _, _, r = s.solve()
+            dt = time.perf_counter() - t
+        nnz = int(qp.q_nnz + qp.a_nnz)
+        out[name] = {"n": int(qp.n), "m": int(qp.m), "nnz": nnz, "status": r["status"],
+                     "iterations": r["iterations"], "rel_kkt": r["rel_kkt"], "seconds": dt,
+                     "iters_per_s": r["iterations"] / dt if dt > 0 else None,
+                     "create_s": create_s}
+        log(f"[bench] class {name}: n={qp.n} m={qp.m} nnz={nnz} (gen {gen_s:.1f}s, create "
+            f"{create_s:.2f}s): status {r['status']}, {r['iterations']} iterations in {dt:.3f}s "
+            f"({r['iterations'] / dt:.0f} it/s), relKKT {r['rel_kkt']:.2e}")
     return out
 
 

@@ -54,6 +54,8 @@ extern "C" {
 #define QP_ITERATION_LIMIT 1  /* max_iter reached */
 #define QP_TIME_LIMIT 2       /* time_limit_s reached */
 #define QP_NUMERICAL_ERROR 3  /* NaN met in the KKT evaluation */
+#define QP_PRIMAL_INFEASIBLE 4 /* certificate found (settings.detect_infeasibility) */
+#define QP_DUAL_INFEASIBLE 5   /* certificate of unbounded descent found (same setting) */
 
 /* qp_settings.restart_mode */
 #define QP_RESTART_ADAPTIVE 0 /* Sec. 6: candidate + criteria (i)-(iii) */
@@ -136,6 +138,25 @@ typedef struct {
                                 the average candidate.  Combined with restart_mode this gives
                                 the four methods of Sec. 5 (PDHG, restarted PDHG, accelerated
                                 PDHG = momentum 1 + QP_RESTART_NONE, rAPDHG). */
+    int32_t precondition;    /* 1: Sec. 5 preprocessing before the iteration: one symmetric
+                                diagonal scaling of K = [[Q, A'], [A, 0]] from ruiz_iters
+                                infinity-norm (Ruiz) steps, one l2-norm step and one
+                                Pock-Chambolle step (alpha = 1); the solver iterates on
+                                D2 Q D2, D1 A D2, D2 c, D1 b, l/D2, u/D2, while relKKT, warm
+                                starts, outputs and the reported objective refer to the given
+                                problem.  0 (default): off */
+    int32_t ruiz_iters;      /* Ruiz steps of the preprocessing; default 10 (Sec. 5) */
+    int32_t detect_infeasibility; /* 1: at every evaluation, test the drift since the last
+                                restart, z - z_restart, for an infeasibility certificate on the
+                                given problem (the paper is silent on infeasible inputs):
+                                QP_PRIMAL_INFEASIBLE when its dual part, projected onto the
+                                dual cone, is a Farkas ray (b'dy > support of X along A'dy,
+                                with every component of A'dy that needs an infinite bound
+                                below eps_infeasible times that margin); QP_DUAL_INFEASIBLE
+                                when its primal part, projected onto the recession cone of X,
+                                descends (c'dx < 0) with ||Q dx||_inf and the row violations
+                                of A dx below eps_infeasible * |c'dx|.  Default 0 */
+    double eps_infeasible;   /* certificate tolerance; default 1e-8 */
 } qp_settings;
 
 typedef struct {
@@ -224,6 +245,11 @@ int qp_get_profile(qp_handle *h, qp_profile *out);
 /* Norms in use by the handle: one value each for a single QP, num_instances values
  * each for a batch (caller-sized host arrays, nullable). */
 int qp_get_norms(qp_handle *h, double *norm_A, double *norm_Q);
+
+/* The Sec. 5 preprocessing scaling in use (settings.precondition = 1): d_var receives
+ * D2 (n values, all instances concatenated for a batch), d_row receives D1 (m values);
+ * host arrays, nullable.  Without preprocessing both are filled with ones. */
+int qp_get_scaling(qp_handle *h, double *d_var, double *d_row);
 
 /* Changes c and/or b (same layout and mem_space as at create; NULL keeps the old
  * vector).  Norm estimates and matrices are unchanged. */

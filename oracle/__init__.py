@@ -19,6 +19,8 @@ from .oracle import (  # noqa: F401
     ITERATION_LIMIT,
     TIME_LIMIT,
     NUMERICAL_ERROR,
+    PRIMAL_INFEASIBLE,
+    DUAL_INFEASIBLE,
     load,
     spmv,
     spmv_t,
@@ -30,4 +32,5 @@ from .oracle import (  # noqa: F401
     solve,
     precondition,
     solve_scaled,
+    infeas_check,
 )

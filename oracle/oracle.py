@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 RESTART_ADAPTIVE, RESTART_FIXED_K, RESTART_HALVING, RESTART_NONE = 0, 1, 2, 3
 OPTIMAL, ITERATION_LIMIT, TIME_LIMIT, NUMERICAL_ERROR = 0, 1, 2, 3
+PRIMAL_INFEASIBLE, DUAL_INFEASIBLE = 4, 5
 
 _pd = C.POINTER(C.c_double)
 _pi = C.POINTER(C.c_int32)
@@ -37,7 +38,12 @@ class _Settings(C.Structure):
                 ("eps_zero", C.c_double), ("step_safety", C.c_double),
                 ("norm_A", C.c_double), ("norm_Q", C.c_double),
                 ("power_iter_max", C.c_int32), ("power_iter_rtol", C.c_double),
-                ("warm_fallback", C.c_int32), ("momentum", C.c_int32)]
+                ("warm_fallback", C.c_int32), ("detect_infeasibility", C.c_int32),
+                ("eps_infeasible", C.c_double), ("momentum", C.c_int32)]
+
+
+class _Infeas(C.Structure):
+    _fields_ = [("primal_ratio", C.c_double), ("dual_ratio", C.c_double)]
 
 
 class _Result(C.Structure):
@@ -79,6 +85,8 @@ class OracleSettings:
     power_iter_max: int = 1000
     power_iter_rtol: float = 1e-7
     warm_fallback: int = 1
+    detect_infeasibility: int = 0
+    eps_infeasible: float = 1e-8
     momentum: int = 1
 
     def _c(self) -> _Settings:
@@ -113,6 +121,8 @@ def load():
                                   _pd, _pd, C.POINTER(_Result), C.POINTER(_CheckLog), C.c_int64,
                                   C.POINTER(C.c_int64)]
         lib.orc_solve.restype = C.c_int
+        lib.orc_infeas_check.argtypes = [C.POINTER(_Problem), _pd, _pd, C.POINTER(_Infeas)]
+        lib.orc_infeas_check.restype = None
         lib.orc_precondition.argtypes = [C.POINTER(_Problem), C.c_int32, C.c_int32, C.c_int32,
                                          _pd, _pd, _pd, _pd, _pd, _pd, _pd, _pd]
         lib.orc_precondition.restype = None
@@ -225,6 +235,16 @@ def run_inner(qp, settings: OracleSettings, nA, nQ, omega, iters, x0=None, y0=No
     load().orc_run_inner(C.byref(pr.s), C.byref(settings._c()), nA, nQ, omega, iters,
                          _ptr(x, _pd), _ptr(y, _pd), _ptr(xb, _pd), _ptr(yb, _pd))
     return x, y[:qp.m], xb, yb[:qp.m]
+
+
+def infeas_check(qp, dx, dy) -> dict:
+    """Certificate ratios of a direction (dx, dy): see orc_infeas_check."""
+    pr = _ProblemRef(qp)
+    dx = _f64(dx)
+    dy = _f64(dy) if qp.m else np.zeros(1)
+    out = _Infeas()
+    load().orc_infeas_check(C.byref(pr.s), _ptr(dx, _pd), _ptr(dy, _pd), C.byref(out))
+    return {"primal_ratio": out.primal_ratio, "dual_ratio": out.dual_ratio}
 
 
 def precondition(qp, ruiz_iters=10, l2=True, pc=True):

@@ -46,6 +46,8 @@ void orc_default_settings(orc_settings *s) {
     s->power_iter_rtol = 1e-7;
     s->warm_fallback = 1;
     s->momentum = 1;
+    s->detect_infeasibility = 0;
+    s->eps_infeasible = 1e-8;
 }
 
 /* ------------------------------------------------------------------ */
@@ -363,6 +365,54 @@ void orc_run_inner(const orc_problem *p, const orc_settings *s, double nA, doubl
 /* ------------------------------------------------------------------ */
 /* full solve: Algorithm 1 inner loop + Sec. 6 / Sec. 5 restart rules  */
 /* ------------------------------------------------------------------ */
+void orc_infeas_check(const orc_problem *p, const double *dx, const double *dy, orc_infeas *out) {
+    const int64_t n = p->n, m = p->m;
+    double *dyp = malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    double *g = malloc(sizeof(double) * (size_t)n);
+    double *dxp = malloc(sizeof(double) * (size_t)n);
+    double *qd = malloc(sizeof(double) * (size_t)n);
+    double *ad = malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    /* primal infeasibility: Farkas direction dy projected onto the dual cone */
+    dyp[0] = 0.0;
+    for (int64_t i = 0; i < m; ++i) dyp[i] = (p->row_type[i] == 1 && dy[i] < 0.0) ? 0.0 : dy[i];
+    orc_spmv_t(m, n, p->a_rowptr, p->a_col, p->a_val, dyp, g);
+    double farkas = 0.0, viol = 0.0;
+    for (int64_t i = 0; i < m; ++i) farkas = farkas + p->b[i] * dyp[i];
+    for (int64_t j = 0; j < n; ++j) {
+        double gj = g[j];
+        if (gj > 0.0) {
+            if (isfinite(p->u[j])) farkas = farkas - p->u[j] * gj;
+            else if (gj > viol) viol = gj;
+        } else if (gj < 0.0) {
+            if (isfinite(p->l[j])) farkas = farkas - p->l[j] * gj;
+            else if (-gj > viol) viol = -gj;
+        }
+    }
+    out->primal_ratio = farkas > 0.0 ? viol / farkas : INFINITY;
+    /* dual infeasibility: recession direction of X with c'dx < 0 */
+    for (int64_t j = 0; j < n; ++j) {
+        int lo = isfinite(p->l[j]), hi = isfinite(p->u[j]);
+        double v = dx[j];
+        if (lo && hi) v = 0.0;
+        else if (lo && v < 0.0) v = 0.0;
+        else if (hi && v > 0.0) v = 0.0;
+        dxp[j] = v;
+    }
+    orc_spmv(n, p->q_rowptr, p->q_col, p->q_val, dxp, qd);
+    orc_spmv(m, p->a_rowptr, p->a_col, p->a_val, dxp, ad);
+    double cdx = 0.0, dv = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        cdx = cdx + p->c[j] * dxp[j];
+        if (fabs(qd[j]) > dv) dv = fabs(qd[j]);
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        double r = p->row_type[i] == 1 ? (ad[i] < 0.0 ? -ad[i] : 0.0) : fabs(ad[i]);
+        if (r > dv) dv = r;
+    }
+    out->dual_ratio = cdx < 0.0 ? dv / -cdx : INFINITY;
+    free(dyp); free(g); free(dxp); free(qd); free(ad);
+}
+
 /* relKKT of (x, y).  Unscaled problem: directly.  Preconditioned problem: the point
  * is mapped back, x = D2 x~, y = D1 y~ (xu, yu are n- and m-sized work arrays), and
  * the error is that of the original problem (Sec. 5 measures the given instance). */
@@ -376,6 +426,33 @@ static void kkt_eval(const orc_problem *p, const orc_problem *orig, const double
     for (int64_t j = 0; j < p->n; ++j) xu[j] = x[j] * dv[j];
     for (int64_t i = 0; i < p->m; ++i) yu[i] = y[i] * dr[i];
     orc_rel_kkt(orig, xu, yu, out);
+}
+
+/* Certificates from the drift since the last restart, z - z_restart, measured on the
+ * given problem (mapped back through D2, D1 when preconditioned). */
+static int infeasible(const orc_problem *p, const orc_problem *orig, const double *dv,
+                      const double *dr, const orc_state *st, const double *x_rs,
+                      const double *y_rs, double *xu, double *yu, double tol, int *status) {
+    const int64_t n = p->n, m = p->m;
+    for (int64_t j = 0; j < n; ++j) {
+        xu[j] = st->x[j] - x_rs[j];
+        if (orig) xu[j] = xu[j] * dv[j];
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        yu[i] = st->y[i] - y_rs[i];
+        if (orig) yu[i] = yu[i] * dr[i];
+    }
+    orc_infeas inf;
+    orc_infeas_check(orig ? orig : p, xu, yu, &inf);
+    if (inf.primal_ratio <= tol) {
+        *status = ORC_PRIMAL_INFEASIBLE;
+        return 1;
+    }
+    if (inf.dual_ratio <= tol) {
+        *status = ORC_DUAL_INFEASIBLE;
+        return 1;
+    }
+    return 0;
 }
 
 static int solve_impl(const orc_problem *p, const orc_problem *orig, const double *dv,
@@ -488,6 +565,10 @@ static int solve_impl(const orc_problem *p, const orc_problem *orig, const doubl
             status = ORC_NUMERICAL_ERROR;
         } else if (rc <= s->eps) {
             status = ORC_OPTIMAL;
+        } else if (s->detect_infeasibility &&
+                   infeasible(p, orig, dv, dr, &st, x_rs, y_rs, xu, yu, s->eps_infeasible,
+                              &status)) {
+            /* status set */
         } else if (total >= s->max_iter) {
             status = ORC_ITERATION_LIMIT;
         } else if (s->time_limit_s > 0.0 && now_s() - t_start >= s->time_limit_s) {

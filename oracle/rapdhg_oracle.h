@@ -33,7 +33,8 @@ typedef struct {
 
 enum { ORC_RESTART_ADAPTIVE = 0, ORC_RESTART_FIXED_K = 1, ORC_RESTART_HALVING = 2,
        ORC_RESTART_NONE = 3 };
-enum { ORC_OPTIMAL = 0, ORC_ITERATION_LIMIT = 1, ORC_TIME_LIMIT = 2, ORC_NUMERICAL_ERROR = 3 };
+enum { ORC_OPTIMAL = 0, ORC_ITERATION_LIMIT = 1, ORC_TIME_LIMIT = 2, ORC_NUMERICAL_ERROR = 3,
+       ORC_PRIMAL_INFEASIBLE = 4, ORC_DUAL_INFEASIBLE = 5 };
 
 typedef struct {
     double eps;              /* relKKT tolerance (Sec. 5, eq. (terminate)) */
@@ -50,6 +51,9 @@ typedef struct {
     int32_t power_iter_max;
     double power_iter_rtol;
     int32_t warm_fallback;   /* 1: keep the warm start only if its relKKT beats the cold start's */
+    int32_t detect_infeasibility; /* 1: test z - z_restart for infeasibility certificates
+                                     at every evaluation (orc_infeas_check) */
+    double eps_infeasible;   /* certificate tolerance (relative, see orc_infeas_check) */
     int32_t momentum;        /* 1: accelerated PDHG weights of Algorithm 1 (default);
                                 0: plain PDHG, the Sec. 5 baseline (beta = theta = 1, constant
                                 step, uniform average of the cycle as restart candidate) */
@@ -109,6 +113,21 @@ void orc_run_inner(const orc_problem *p, const orc_settings *s, double norm_A, d
 int orc_solve(const orc_problem *p, const orc_settings *s, const double *x0, const double *y0,
               double omega0, double *x_out, double *y_out, orc_result *res,
               orc_check_log *check_log, int64_t log_cap, int64_t *log_len);
+
+/* Infeasibility certificates from a direction (dx, dy) (the paper is silent; the
+ * drift of the iterates of an infeasible problem is such a direction).
+ *  primal_ratio: dy is projected onto the dual cone (GE rows >= 0) giving dy+, g = A'dy+;
+ *    farkas = b'dy+ - sum over finite bounds of the support of X in direction g
+ *    (u_j g_j for g_j > 0, l_j g_j for g_j < 0); viol = max |g_j| over the components
+ *    whose needed bound is infinite; ratio = viol / farkas if farkas > 0 else +inf.
+ *    A ratio of 0 is an exact Farkas certificate: b'y > sup_{x in X} (A'y)'x.
+ *  dual_ratio: dx is projected onto the recession cone of X giving dx+;
+ *    cdx = c'dx+; viol = max(||Q dx+||_inf, ||(A dx+)_EQ||_inf, ||[-(A dx+)_GE]_+||_inf);
+ *    ratio = viol / (-cdx) if cdx < 0 else +inf: a direction of unbounded descent. */
+typedef struct {
+    double primal_ratio, dual_ratio;
+} orc_infeas;
+void orc_infeas_check(const orc_problem *p, const double *dx, const double *dy, orc_infeas *out);
 
 /* Diagonal preconditioning (Sec. 5 "Preprocessing"): ruiz_iters infinity-norm
  * (Ruiz) steps, then one l2-norm step if l2, then one Pock-Chambolle (alpha = 1)

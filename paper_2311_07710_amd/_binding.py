@@ -21,6 +21,7 @@ QP_ERR_BATCH_MISMATCH = 4
 QP_ERR_UNSUPPORTED = 5
 
 QP_OPTIMAL, QP_ITERATION_LIMIT, QP_TIME_LIMIT, QP_NUMERICAL_ERROR = 0, 1, 2, 3
+QP_PRIMAL_INFEASIBLE, QP_DUAL_INFEASIBLE = 4, 5
 QP_RESTART_ADAPTIVE, QP_RESTART_FIXED_K, QP_RESTART_HALVING, QP_RESTART_NONE = 0, 1, 2, 3
 QP_MEM_HOST, QP_MEM_DEVICE = 0, 1
 
@@ -48,7 +49,8 @@ class qp_settings(C.Structure):
                 ("power_iter_rtol", C.c_double), ("warm_fallback", C.c_int32),
                 ("use_graph", C.c_int32), ("profile", C.c_int32), ("log_checks", C.c_int32),
                 ("device", C.c_int32), ("panels_dual", C.c_int32), ("panels_primal", C.c_int32),
-                ("momentum", C.c_int32)]
+                ("momentum", C.c_int32), ("precondition", C.c_int32), ("ruiz_iters", C.c_int32),
+                ("detect_infeasibility", C.c_int32), ("eps_infeasible", C.c_double)]
 
 
 class qp_warm_start(C.Structure):
@@ -85,6 +87,7 @@ SIGNATURES = {
                                    C.POINTER(C.c_int64)]),
     "qp_get_profile": (C.c_int, [_vp, C.POINTER(qp_profile)]),
     "qp_get_norms": (C.c_int, [_vp, _vp, _vp]),
+    "qp_get_scaling": (C.c_int, [_vp, _vp, _vp]),
     "qp_update_vectors": (C.c_int, [_vp, _vp, _vp]),
     "qp_set_norms": (C.c_int, [_vp, _vp, _vp]),
     "qp_batch_autotune": (C.c_int, [_vp, C.c_int32, C.c_int32, _vp]),

@@ -343,6 +343,9 @@ struct qp_handle {
     // problem data
     DevMem a_rowptr, a_col, a_val, p_rowptr, p_col, p_val;
     DevMem c, b, l, u, rt;
+    DevMem dscale;              // preconditioning d = (D2 [n], D1 [m]) on the device
+    std::vector<double> h_d;    // its host copy (empty: not preconditioned)
+    std::vector<double> h_c, h_b;  // the given c and b (host copies)
     DevPartition partA, partP;
     DevPanels panA, panP;    // column-panel layouts of A and P (np > 1)
     int npA = 1, npP = 1;
@@ -353,6 +356,7 @@ struct qp_handle {
     // solver vectors
     DevMem x, xbar, xt, xmd0, xmd1, xrs, y, ybar, yrs, x0buf, y0buf;
     DevMem partials_a, partials_p, state, table;
+    DevMem ipart_a, ipart_p;    // infeasibility partials (when detection is on)
     Vecs vecs{};
     int32_t nslotA = 0, nslotP = 0;
     State *h_state = nullptr;  // pinned ring of status records
@@ -411,6 +415,10 @@ void qp_default_settings(qp_settings *s) {
     s->panels_dual = 0;
     s->panels_primal = 0;
     s->momentum = 1;
+    s->precondition = 0;
+    s->ruiz_iters = 10;
+    s->detect_infeasibility = 0;
+    s->eps_infeasible = 1e-8;
 }
 
 const char *qp_last_error(void) { return qph::g_err.c_str(); }
@@ -433,6 +441,14 @@ int check_settings(const qp_settings &s) {
     if (!(s.step_safety > 0.0)) return fail(QP_ERR_INVALID_ARGUMENT, "step_safety must be > 0");
     if (s.momentum != 0 && s.momentum != 1)
         return fail(QP_ERR_INVALID_ARGUMENT, "momentum must be 0 or 1");
+    if (s.precondition != 0 && s.precondition != 1)
+        return fail(QP_ERR_INVALID_ARGUMENT, "precondition must be 0 or 1");
+    if (s.ruiz_iters < 0 || s.ruiz_iters > 100)
+        return fail(QP_ERR_INVALID_ARGUMENT, "ruiz_iters must be in [0, 100]");
+    if (s.detect_infeasibility != 0 && s.detect_infeasibility != 1)
+        return fail(QP_ERR_INVALID_ARGUMENT, "detect_infeasibility must be 0 or 1");
+    if (!(s.eps_infeasible > 0.0))
+        return fail(QP_ERR_INVALID_ARGUMENT, "eps_infeasible must be > 0");
     return QP_OK;
 }
 
@@ -506,15 +522,43 @@ int estimate_norms(qp_handle *h) {
     return QP_OK;
 }
 
-int set_vectors_host_stats(qp_handle *h, const std::vector<double> &c, const std::vector<double> &b) {
-    double cn = 0.0, bn = 0.0, ci = 0.0, bi = 0.0;
-    for (double v : c) {
-        cn += v * v;
-        if (std::fabs(v) > ci) ci = std::fabs(v);
+// Uploads c and b (and the bounds when given) of the problem the iteration runs on:
+// the given vectors, or with preconditioning c~ = D2 c, b~ = D1 b, l~ = l / D2,
+// u~ = u / D2.  relKKT's ||c||_inf and ||b||_inf are the given problem's; the 2-norms
+// for the initial primal weight are those of the iterated (scaled) problem.
+int upload_vectors(qp_handle *h, const std::vector<double> &c, const std::vector<double> &b,
+                   const std::vector<double> *l, const std::vector<double> *u) {
+    const int64_t n = h->n, m = h->m;
+    const bool sc = !h->h_d.empty();
+    std::vector<double> cs(c), bs(b);
+    if (sc) {
+        for (int64_t j = 0; j < n; ++j) cs[j] = c[j] * h->h_d[j];
+        for (int64_t i = 0; i < m; ++i) bs[i] = b[i] * h->h_d[n + i];
     }
-    for (double v : b) {
-        bn += v * v;
-        if (std::fabs(v) > bi) bi = std::fabs(v);
+    auto put = [&](DevMem &dm, const std::vector<double> &v) -> int {
+        if (!dm.p) return dm.upload(v.data(), v.size() * 8);
+        if (!v.empty()) HIPCHK(hipMemcpy(dm.p, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+        return QP_OK;
+    };
+    int rc;
+    if ((rc = put(h->c, cs)) || (rc = put(h->b, bs))) return rc;
+    if (l && u) {
+        std::vector<double> ls(*l), us(*u);
+        if (sc)
+            for (int64_t j = 0; j < n; ++j) {
+                ls[j] = (*l)[j] / h->h_d[j];
+                us[j] = (*u)[j] / h->h_d[j];
+            }
+        if ((rc = put(h->l, ls)) || (rc = put(h->u, us))) return rc;
+    }
+    double cn = 0.0, bn = 0.0, ci = 0.0, bi = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        cn += cs[j] * cs[j];
+        if (std::fabs(c[j]) > ci) ci = std::fabs(c[j]);
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        bn += bs[i] * bs[i];
+        if (std::fabs(b[i]) > bi) bi = std::fabs(b[i]);
     }
     h->c_norm2 = std::sqrt(cn);
     h->b_norm2 = std::sqrt(bn);
@@ -623,12 +667,47 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
     if ((rc = up(h->a_rowptr, ar.data(), ar.size() * 4)) || (rc = up(h->a_col, ac.data(), ac.size() * 4)) ||
         (rc = up(h->a_val, av.data(), av.size() * 8)) || (rc = up(h->p_rowptr, pr.data(), pr.size() * 4)) ||
         (rc = up(h->p_col, pc.data(), pc.size() * 4)) || (rc = up(h->p_val, pv.data(), pv.size() * 8)) ||
-        (rc = up(h->c, c.data(), n * 8)) || (rc = up(h->b, b.data(), b.size() * 8)) ||
-        (rc = up(h->l, l.data(), n * 8)) || (rc = up(h->u, u.data(), n * 8)) ||
         (rc = up(h->rt, rt.data(), rt.size())))
         return rc;
     h->A = Csr{h->a_rowptr.as<int32_t>(), h->a_col.as<int32_t>(), h->a_val.as<double>(), m};
     h->P = Csr{h->p_rowptr.as<int32_t>(), h->p_col.as<int32_t>(), h->p_val.as<double>(), n};
+    // Sec. 5 preprocessing: scale A and P in place on the device; the panel copies below
+    // are built from the scaled values
+    std::vector<double> av_s, pv_s;
+    const double *avp = av.data(), *pvp = pv.data();
+    if (h->set.precondition) {
+        DevMem work;
+        if ((rc = work.alloc((size_t)(n + m) * 16)) || (rc = h->dscale.alloc((size_t)(n + m) * 8)))
+            return rc;
+        ScaleInput in{};
+        in.n = n;
+        in.m = m;
+        in.a_rowptr = h->A.rowptr;
+        in.a_col = h->A.col;
+        in.a_val = h->a_val.as<double>();
+        in.p_rowptr = h->P.rowptr;
+        in.p_col = h->P.col;
+        in.p_val = h->p_val.as<double>();
+        in.ruiz_iters = h->set.ruiz_iters;
+        in.l2 = 1;
+        in.pc = 1;
+        if (precondition_device(h->stream, in, work.as<double>(), h->dscale.as<double>()))
+            return fail(QP_ERR_DEVICE, "preconditioning kernels failed to launch");
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->h_d.resize((size_t)(n + m));
+        HIPCHK(hipMemcpy(h->h_d.data(), h->dscale.p, (size_t)(n + m) * 8, hipMemcpyDeviceToHost));
+        av_s.resize(av.size());
+        pv_s.resize(pv.size());
+        if (!av_s.empty())
+            HIPCHK(hipMemcpy(av_s.data(), h->a_val.p, av_s.size() * 8, hipMemcpyDeviceToHost));
+        if (!pv_s.empty())
+            HIPCHK(hipMemcpy(pv_s.data(), h->p_val.p, pv_s.size() * 8, hipMemcpyDeviceToHost));
+        avp = av_s.data();
+        pvp = pv_s.data();
+    }
+    h->h_c = c;
+    h->h_b = b;
+    if ((rc = upload_vectors(h, c, b, &l, &u))) return rc;
     HostPartition hpA = partition_rows(ar.data(), m), hpP = partition_rows(pr.data(), n);
     {
         // Algorithmic bytes of one launch: matrix values (8 B) + column indices (4 B) per
@@ -653,14 +732,13 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
     h->npA = m > 0 ? choose_panels(h->set.panels_dual, n) : 1;
     h->npP = choose_panels(h->set.panels_primal, n + m);
     if (h->npA > 1) {
-        HostPanels pa = build_panels(ar.data(), ac.data(), av.data(), m, n, h->npA);
+        HostPanels pa = build_panels(ar.data(), ac.data(), avp, m, n, h->npA);
         if ((rc = h->panA.upload(pa, m))) return rc;
     }
     if (h->npP > 1) {
-        HostPanels pp = build_panels(pr.data(), pc.data(), pv.data(), n, n + m, h->npP);
+        HostPanels pp = build_panels(pr.data(), pc.data(), pvp, n, n + m, h->npP);
         if ((rc = h->panP.upload(pp, n))) return rc;
     }
-    set_vectors_host_stats(h, c, b);
 
     // solver vectors
     const size_t nb = (size_t)n * 8, mb = (size_t)std::max<int64_t>(m, 1) * 8;
@@ -674,6 +752,10 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
     if ((rc = h->partials_a.alloc((size_t)(h->nslotA + FOLD_SLOTS) * RA_NV * 8)) ||
         (rc = h->partials_p.alloc((size_t)(h->nslotP + FOLD_SLOTS) * RP_NV * 8)) ||
         (rc = h->state.alloc(sizeof(State))) || (rc = h->table.alloc(4096 * sizeof(Step))))
+        return rc;
+    if (h->set.detect_infeasibility &&
+        ((rc = h->ipart_a.alloc((size_t)(h->nslotA + FOLD_SLOTS) * IA_NV * 8)) ||
+         (rc = h->ipart_p.alloc((size_t)(h->nslotP + FOLD_SLOTS) * IP_NV * 8))))
         return rc;
     Vecs &v = h->vecs;
     v.x = h->x.as<double>();
@@ -690,6 +772,8 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
     v.l = h->l.as<double>();
     v.u = h->u.as<double>();
     v.rt = h->rt.as<uint8_t>();
+    v.dv = h->h_d.empty() ? nullptr : h->dscale.as<double>();
+    v.dr = h->h_d.empty() ? nullptr : h->dscale.as<double>() + n;
     return QP_OK;
 }
 
@@ -713,6 +797,8 @@ DevSettings dev_settings(const qp_handle *h) {
     ds.fixed_K = s.fixed_K;
     ds.interval = s.restart_mode == QP_RESTART_FIXED_K ? s.fixed_K : s.check_every;
     ds.momentum = s.momentum;
+    ds.detect_infeas = s.detect_infeasibility;
+    ds.eps_infeas = s.eps_infeasible;
     return ds;
 }
 
@@ -734,6 +820,10 @@ void enqueue_interval(qp_handle *h, const DevSettings &ds, int md_in, int len, b
     }
     launch_kkt_rows(s, h->partA.view, h->A, h->vecs, h->partials_a.as<double>(), st);
     launch_kkt_cols(s, h->partP.view, h->P, h->vecs, h->partials_p.as<double>(), st, h->n);
+    if (h->set.detect_infeasibility)  // directions in the warm-start buffers (free here)
+        launch_infeas(s, h->partA.view, h->A, h->partP.view, h->P, h->vecs,
+                      h->x0buf.as<double>(), h->y0buf.as<double>(), h->ipart_a.as<double>(),
+                      h->nslotA, h->ipart_p.as<double>(), h->nslotP, st, h->n, h->m);
     launch_decide(s, DECIDE_CHECK, h->partials_a.as<double>(), h->nslotA,
                   h->partials_p.as<double>(), h->nslotP, st, h->table.as<Step>(), ds, len);
     launch_apply(s, h->vecs, md, st, h->n, h->m);
@@ -861,6 +951,14 @@ void qp_free(qp_handle *h) {
     delete h;
 }
 
+int qp_get_scaling(qp_handle *h, double *d_var, double *d_row) {
+    if (!h) return fail(QP_ERR_INVALID_ARGUMENT, "null handle");
+    if (h->batch) return qpb::batch_scaling(h->batch, d_var, d_row);
+    for (int64_t j = 0; d_var && j < h->n; ++j) d_var[j] = h->h_d.empty() ? 1.0 : h->h_d[j];
+    for (int64_t i = 0; d_row && i < h->m; ++i) d_row[i] = h->h_d.empty() ? 1.0 : h->h_d[h->n + i];
+    return QP_OK;
+}
+
 int qp_get_norms(qp_handle *h, double *norm_A, double *norm_Q) {
     if (!h) return fail(QP_ERR_INVALID_ARGUMENT, "null handle");
     if (h->batch) return qpb::batch_norms(h->batch, norm_A, norm_Q);
@@ -873,14 +971,21 @@ int qp_update_vectors(qp_handle *h, const double *c, const double *b) {
     if (!h) return fail(QP_ERR_INVALID_ARGUMENT, "null handle");
     HIPCHK(hipSetDevice(h->device));
     if (h->batch) return qpb::batch_update_vectors(h->batch, c, b, h->mem_space);
-    const hipMemcpyKind kind = h->mem_space == QP_MEM_HOST ? hipMemcpyHostToDevice
-                                                           : hipMemcpyDeviceToDevice;
-    if (c) HIPCHK(hipMemcpy(h->c.p, c, h->n * 8, kind));
-    if (b && h->m) HIPCHK(hipMemcpy(h->b.p, b, h->m * 8, kind));
     std::vector<double> hc(h->n), hb(h->m);
-    HIPCHK(hipMemcpy(hc.data(), h->c.p, h->n * 8, hipMemcpyDeviceToHost));
-    if (h->m) HIPCHK(hipMemcpy(hb.data(), h->b.p, h->m * 8, hipMemcpyDeviceToHost));
-    return set_vectors_host_stats(h, hc, hb);
+    int rc;
+    if (c) {
+        if ((rc = fetch(hc, c, h->n, h->mem_space))) return rc;
+    } else {
+        hc = h->h_c;
+    }
+    if (b && h->m) {
+        if ((rc = fetch(hb, b, h->m, h->mem_space))) return rc;
+    } else {
+        hb = h->h_b;
+    }
+    h->h_c = hc;
+    h->h_b = hb;
+    return upload_vectors(h, hc, hb, nullptr, nullptr);
 }
 
 int qp_set_norms(qp_handle *h, const double *norm_A, const double *norm_Q) {
@@ -952,13 +1057,17 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
     if (ws && (ws->x0 || ws->y0)) {
         const hipMemcpyKind kind = h->mem_space == QP_MEM_HOST ? hipMemcpyHostToDevice
                                                                : hipMemcpyDeviceToDevice;
+        const bool sc = !h->h_d.empty();  // warm starts refer to the given problem
         if (ws->x0) {
             HIPCHK(hipMemcpyAsync(h->x0buf.p, ws->x0, n * 8, kind, s));
             x0 = h->x0buf.as<double>();
+            if (sc) launch_scale_pair(s, h->x0buf.as<double>(), x0, h->dscale.as<double>(), n, 1);
         }
         if (ws->y0 && m) {
             HIPCHK(hipMemcpyAsync(h->y0buf.p, ws->y0, m * 8, kind, s));
             y0 = h->y0buf.as<double>();
+            if (sc)
+                launch_scale_pair(s, h->y0buf.as<double>(), y0, h->dscale.as<double>() + n, m, 1);
         }
     }
     const bool warm = ws && (ws->x0 || ws->y0);
@@ -1069,6 +1178,13 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
                                                            : hipMemcpyDeviceToDevice;
     const double *xs = last.cand ? h->vecs.xbar : h->vecs.x;
     const double *ys = last.cand ? h->vecs.ybar : h->vecs.y;
+    if (!h->h_d.empty()) {  // back to the given problem: x = D2 x~, y = D1 y~
+        launch_scale_pair(s, h->x0buf.as<double>(), xs, h->dscale.as<double>(), n, 0);
+        if (m) launch_scale_pair(s, h->y0buf.as<double>(), ys, h->dscale.as<double>() + n, m, 0);
+        HIPCHK(hipStreamSynchronize(s));
+        xs = h->x0buf.as<double>();
+        ys = h->y0buf.as<double>();
+    }
     if (x_out) HIPCHK(hipMemcpy(x_out, xs, n * 8, kind));
     if (y_out && m) HIPCHK(hipMemcpy(y_out, ys, m * 8, kind));
     fill_result(h, last, now_s() - t0, res);

@@ -16,6 +16,7 @@ void destroy_batch(BatchData *b);
 int batch_solve(BatchData *b, const qp_settings *s, int mem_space, const qp_warm_start *ws,
                 qp_result *res, double *x_out, double *y_out);
 int batch_norms(BatchData *b, double *norm_A, double *norm_Q);
+int batch_scaling(BatchData *b, double *d_var, double *d_row);
 int batch_update_vectors(BatchData *b, const double *c, const double *bvec, int mem_space);
 int batch_set_norms(BatchData *b, const double *norm_A, const double *norm_Q);
 int batch_autotune(BatchData *b, const qp_settings *s, int32_t sample, int32_t iters,

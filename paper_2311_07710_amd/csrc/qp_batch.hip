@@ -65,6 +65,8 @@ struct BatchDev {
     // rows longer than LONG_ROW nonzeros are reduced by the whole team
     const int32_t *lrA_off, *lrA;  // per instance [off[i], off[i+1]) into local A row ids
     const int32_t *lrP_off, *lrP;  // same for rows of P
+    const double *dscale;          // preconditioning: D2 of all variables, then D1; or nullptr
+    int64_t ntot;                  // variables of all instances
 };
 
 constexpr int LONG_ROW = 128;
@@ -121,20 +123,24 @@ __device__ void team_sum(double *v, double *red) {
 }
 
 // per-row KKT contributions (rows of A: primal residuals, |Ax|, b'y, restart distances)
+// dr / dv: the instance's preconditioning D1 / D2 (nullptr: none); the infinity norms
+// are those of the given problem, whose row i is the scaled row divided by D1_i and whose
+// column j is the scaled one divided by D2_j (dot products are invariant).
 __device__ __forceinline__ void kkt_row_contrib(int i, double s0, double s1, const double *b,
                                                 const uint8_t *rt, const double *y,
                                                 const double *ybar, const double *yrs,
-                                                double *ra) {
+                                                const double *dr, double *ra) {
     const double bi = b[i];
     double r0 = s0 - bi, r1 = s1 - bi;
     if (rt[i] == 1) {
         r0 = (r0 < 0.0) ? -r0 : 0.0;
         r1 = (r1 < 0.0) ? -r1 : 0.0;
     }
-    ra[RA_RES0] = bmax(ra[RA_RES0], fabs(r0));
-    ra[RA_RES1] = bmax(ra[RA_RES1], fabs(r1));
-    ra[RA_AX0] = bmax(ra[RA_AX0], fabs(s0));
-    ra[RA_AX1] = bmax(ra[RA_AX1], fabs(s1));
+    const double sr = dr ? dr[i] : 1.0;
+    ra[RA_RES0] = bmax(ra[RA_RES0], fabs(r0) / sr);
+    ra[RA_RES1] = bmax(ra[RA_RES1], fabs(r1) / sr);
+    ra[RA_AX0] = bmax(ra[RA_AX0], fabs(s0) / sr);
+    ra[RA_AX1] = bmax(ra[RA_AX1], fabs(s1) / sr);
     const double yi = y[i], ybi = ybar[i], yr = yrs[i];
     ra[RA_BY0] += bi * yi;
     ra[RA_BY1] += bi * ybi;
@@ -148,9 +154,10 @@ __device__ __forceinline__ void kkt_col_contrib(int j, const double *q, const do
                                                 const double *c, const double *l,
                                                 const double *u, const double *x,
                                                 const double *xbar, const double *xrs,
-                                                double *rp) {
+                                                const double *dv, double *rp) {
     const double cj = c[j], lj = l[j], uj = u[j];
     const bool lo_fin = isfinite(lj), hi_fin = isfinite(uj);
+    const double sv = dv ? dv[j] : 1.0;
     for (int p = 0; p < 2; ++p) {
         const double xp = p == 0 ? x[j] : xbar[j];
         const double aty = -na[p];
@@ -160,9 +167,9 @@ __device__ __forceinline__ void kkt_col_contrib(int j, const double *q, const do
         else if (lo_fin) lam_hat = lam > 0.0 ? lam : 0.0;
         else if (hi_fin) lam_hat = lam < 0.0 ? lam : 0.0;
         else lam_hat = 0.0;
-        rp[RP_DRES0 + p] = bmax(rp[RP_DRES0 + p], fabs(lam - lam_hat));
-        rp[RP_QX0 + p] = bmax(rp[RP_QX0 + p], fabs(q[p]));
-        rp[RP_ATY0 + p] = bmax(rp[RP_ATY0 + p], fabs(aty));
+        rp[RP_DRES0 + p] = bmax(rp[RP_DRES0 + p], fabs(lam - lam_hat) / sv);
+        rp[RP_QX0 + p] = bmax(rp[RP_QX0 + p], fabs(q[p]) / sv);
+        rp[RP_ATY0 + p] = bmax(rp[RP_ATY0 + p], fabs(aty) / sv);
         rp[RP_XQX0 + p] += xp * q[p];
         rp[RP_CX0 + p] += cj * xp;
         double bnd = 0.0;
@@ -194,6 +201,99 @@ __device__ __forceinline__ double row_dot(const int32_t *__restrict__ col,
     return s;
 }
 
+// Infeasibility quantities (State::inf order) of the drift z - z_restart of one instance,
+// projected onto the dual cone (dy+) and the recession cone of X (dx+); result in
+// thread 0's out.  Same row/column contributions as the single-instance kernels.
+template <int NT>
+__device__ __forceinline__ void team_infeas(int n, int m, const int32_t *arp, const int32_t *acol,
+                                         const double *aval, const int32_t *prp,
+                                         const int32_t *pcol, const double *pval,
+                                         const double *c, const double *b, const double *l,
+                                         const double *u, const uint8_t *rt, const double *x,
+                                         const double *xrs, const double *y, const double *yrs,
+                                         const double *dv, const double *dr, const int32_t *lra,
+                                         int nlra, const int32_t *lrp, int nlrp, double *red,
+                                         double *out) {
+    auto dxh = [&](int j) {
+        const bool lo = isfinite(l[j]), hi = isfinite(u[j]);
+        double v = x[j] - xrs[j];
+        if (lo && hi) v = 0.0;
+        else if (lo && v < 0.0) v = 0.0;
+        else if (hi && v > 0.0) v = 0.0;
+        return v;
+    };
+    auto dyh = [&](int i) {
+        const double v = y[i] - yrs[i];
+        return (rt[i] == 1 && v < 0.0) ? 0.0 : v;
+    };
+    // cv: 0 A dx+ violation, 1 |Q dx+|, 2 |A'dy+| needing an infinite bound (maxima);
+    //     3 b'dy+, 4 support of X along A'dy+, 5 c'dx+ (sums)
+    double cv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    auto row = [&](int i, double sa) {
+        const double viol = rt[i] == 1 ? (sa < 0.0 ? -sa : 0.0) : fabs(sa);
+        cv[0] = bmax(cv[0], viol / (dr ? dr[i] : 1.0));
+        cv[3] += b[i] * dyh(i);
+    };
+    auto col = [&](int j, double qd, double nat) {
+        const double sv = dv ? dv[j] : 1.0;
+        const double g = -nat;
+        double viol = 0.0, supp = 0.0;
+        if (g > 0.0) {
+            if (isfinite(u[j])) supp = u[j] * g;
+            else viol = g;
+        } else if (g < 0.0) {
+            if (isfinite(l[j])) supp = l[j] * g;
+            else viol = -g;
+        }
+        cv[1] = bmax(cv[1], fabs(qd) / sv);
+        cv[2] = bmax(cv[2], viol / sv);
+        cv[4] += supp;
+        cv[5] += c[j] * dxh(j);
+    };
+    for (int i = threadIdx.x; i < m; i += NT) {
+        if (arp[i + 1] - arp[i] > LONG_ROW) continue;
+        row(i, row_dot(acol, aval, arp[i], arp[i + 1], dxh));
+    }
+    for (int q = 0; q < nlra; ++q) {
+        const int i = lra[q];
+        double sv[1] = {0.0};
+        for (int e = arp[i] + threadIdx.x; e < arp[i + 1]; e += NT)
+            sv[0] = sv[0] + aval[e] * dxh(acol[e]);
+        team_sum<NT, 1>(sv, red);
+        if (threadIdx.x == 0) row(i, sv[0]);
+    }
+    for (int j = threadIdx.x; j < n; j += NT) {
+        if (prp[j + 1] - prp[j] > LONG_ROW) continue;
+        double qd = 0.0, na = 0.0;
+        for (int e = prp[j]; e < prp[j + 1]; ++e) {
+            const int cc = pcol[e];
+            if (cc < n) qd = qd + pval[e] * dxh(cc);
+            else na = na + pval[e] * dyh(cc - n);
+        }
+        col(j, qd, na);
+    }
+    for (int q = 0; q < nlrp; ++q) {
+        const int j = lrp[q];
+        double sv[2] = {0.0, 0.0};
+        for (int e = prp[j] + threadIdx.x; e < prp[j + 1]; e += NT) {
+            const int cc = pcol[e];
+            if (cc < n) sv[0] = sv[0] + pval[e] * dxh(cc);
+            else sv[1] = sv[1] + pval[e] * dyh(cc - n);
+        }
+        team_sum<NT, 2>(sv, red);
+        if (threadIdx.x == 0) col(j, sv[0], sv[1]);
+    }
+    team_reduce<NT>(cv, 6, 3, red);
+    if (threadIdx.x == 0) {
+        out[INF_AVIOL] = cv[0];
+        out[INF_QDX] = cv[1];
+        out[INF_GVIOL] = cv[2];
+        out[INF_BDY] = cv[3];
+        out[INF_SUPP] = cv[4];
+        out[INF_CDX] = cv[5];
+    }
+}
+
 // KKT quantities of z = (x, y) and z-bar for one instance; results in thread 0's ra/rp.
 // Rows up to LONG_ROW nonzeros: one thread each; longer rows: the whole team.
 template <int NT>
@@ -203,7 +303,8 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
                          const uint8_t *rt, const double *x, const double *xbar,
                          const double *xrs, const double *y, const double *ybar,
                          const double *yrs, double *ra, double *rp, double *red,
-                         const int32_t *lra, int nlra, const int32_t *lrp, int nlrp) {
+                         const int32_t *lra, int nlra, const int32_t *lrp, int nlrp,
+                         const double *dv, const double *dr) {
     for (int v = 0; v < RA_NV; ++v) ra[v] = 0.0;
     for (int i = threadIdx.x; i < m; i += NT) {
         if (arp[i + 1] - arp[i] > LONG_ROW) continue;
@@ -214,7 +315,7 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
             s0 = s0 + a * x[cc];
             s1 = s1 + a * xbar[cc];
         }
-        kkt_row_contrib(i, s0, s1, b, rt, y, ybar, yrs, ra);
+        kkt_row_contrib(i, s0, s1, b, rt, y, ybar, yrs, dr, ra);
     }
     for (int q = 0; q < nlra; ++q) {
         const int i = lra[q];
@@ -226,7 +327,7 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
             sv[1] = sv[1] + a * xbar[cc];
         }
         team_sum<NT, 2>(sv, red);
-        if (threadIdx.x == 0) kkt_row_contrib(i, sv[0], sv[1], b, rt, y, ybar, yrs, ra);
+        if (threadIdx.x == 0) kkt_row_contrib(i, sv[0], sv[1], b, rt, y, ybar, yrs, dr, ra);
     }
     team_reduce<NT>(ra, RA_NV, 4, red);
     for (int v = 0; v < RP_NV; ++v) rp[v] = 0.0;
@@ -244,7 +345,7 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
                 na[1] = na[1] + a * ybar[cc - n];
             }
         }
-        kkt_col_contrib(j, q, na, c, l, u, x, xbar, xrs, rp);
+        kkt_col_contrib(j, q, na, c, l, u, x, xbar, xrs, dv, rp);
     }
     for (int qq = 0; qq < nlrp; ++qq) {
         const int j = lrp[qq];
@@ -263,7 +364,7 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
         team_sum<NT, 4>(sv, red);
         if (threadIdx.x == 0) {
             double q[2] = {sv[0], sv[1]}, na[2] = {sv[2], sv[3]};
-            kkt_col_contrib(j, q, na, c, l, u, x, xbar, xrs, rp);
+            kkt_col_contrib(j, q, na, c, l, u, x, xbar, xrs, dv, rp);
         }
     }
     team_reduce<NT>(rp, RP_NV, 6, red);
@@ -328,6 +429,8 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
         double *xt = in_lds ? smem : a.xt + v0;
         double *xmd[2] = {in_lds ? smem + n : a.xmd0 + v0, in_lds ? smem + 2 * n : a.xmd1 + v0};
         double *y = in_lds ? smem + 3 * n : a.y + r0;
+        const double *dvi = a.dscale ? a.dscale + v0 : nullptr;
+        const double *dri = a.dscale ? a.dscale + a.ntot + r0 : nullptr;
         const int32_t *lra = a.lrA + a.lrA_off[id];
         const int nlra = a.lrA_off[id + 1] - a.lrA_off[id];
         const int32_t *lrp = a.lrP + a.lrP_off[id];
@@ -375,7 +478,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
         double ra[RA_NV], rp[RP_NV];
         if (pair) {
             team_kkt<NT>(n, m, arp, a.a_col, a.a_val, prp, a.p_col, a.p_val, c, b, l, u, rt, x,
-                         xbar, xrs, y, ybar, yrs, ra, rp, red, lra, nlra, lrp, nlrp);
+                         xbar, xrs, y, ybar, yrs, ra, rp, red, lra, nlra, lrp, nlrp, dvi, dri);
             if (t == 0) batch_decide(DECIDE_FALLBACK, ra, rp, &S, &ds, 0);
             __syncthreads();
             const int take = S.used_warm;
@@ -390,7 +493,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
             __syncthreads();
         }
         team_kkt<NT>(n, m, arp, a.a_col, a.a_val, prp, a.p_col, a.p_val, c, b, l, u, rt, x, xbar,
-                     xrs, y, ybar, yrs, ra, rp, red, lra, nlra, lrp, nlrp);
+                     xrs, y, ybar, yrs, ra, rp, red, lra, nlra, lrp, nlrp, dvi, dri);
         if (t == 0) {
             batch_decide(DECIDE_INIT, ra, rp, &S, &ds, 0);
             double sl = 0.0;
@@ -460,7 +563,10 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
                 md ^= 1;
             }
             team_kkt<NT>(n, m, arp, a.a_col, a.a_val, prp, a.p_col, a.p_val, c, b, l, u, rt, x,
-                         xbar, xrs, y, ybar, yrs, ra, rp, red, lra, nlra, lrp, nlrp);
+                         xbar, xrs, y, ybar, yrs, ra, rp, red, lra, nlra, lrp, nlrp, dvi, dri);
+            if (ds.detect_infeas)
+                team_infeas<NT>(n, m, arp, a.a_col, a.a_val, prp, a.p_col, a.p_val, c, b, l, u,
+                                rt, x, xrs, y, yrs, dvi, dri, lra, nlra, lrp, nlrp, red, S.inf);
             if (t == 0) {
                 batch_decide(DECIDE_CHECK, ra, rp, &S, &ds, len);
                 if (!S.done && a.deadline_ticks > 0 &&
@@ -659,6 +765,9 @@ struct BatchData {
     DevMem var_off_d, row_off_d, a_rowptr, a_col, a_val, p_rowptr, p_col, p_val;
     DevMem c, b, l, u, rt, normA_d, normQ_d, b_inf_d, c_inf_d, omega0_d, has_x0, has_y0, x0, y0;
     DevMem x, xbar, xt, xmd0, xmd1, xrs, y, ybar, yrs, x_out, y_out, res, order_d, head, clock0;
+    DevMem dscale;                   // preconditioning (D2 of all variables, then D1), or empty
+    std::vector<double> h_d;         // host copy of dscale (empty: not preconditioned)
+    std::vector<double> h_c, h_b;    // the given c and b
     DevMem lrA_off, lrA, lrP_off, lrP;  // long-row lists (rows > LONG_ROW nonzeros)
     std::vector<int32_t> order_off;  // offsets of each class in order_d
     std::vector<double> h_omega;     // staging of per-solve scalars (outlive async copies)
@@ -719,6 +828,8 @@ static BatchDev make_dev(BatchData *bd) {
     a.lrA = bd->lrA.as<int32_t>();
     a.lrP_off = bd->lrP_off.as<int32_t>();
     a.lrP = bd->lrP.as<int32_t>();
+    a.dscale = bd->h_d.empty() ? nullptr : bd->dscale.as<double>();
+    a.ntot = bd->ntot;
     return a;
 }
 
@@ -784,6 +895,8 @@ static DevSettings batch_settings(const qp_settings *s) {
     ds.fixed_K = s->fixed_K;
     ds.interval = s->restart_mode == QP_RESTART_FIXED_K ? s->fixed_K : s->check_every;
     ds.momentum = s->momentum;
+    ds.detect_infeas = s->detect_infeasibility;
+    ds.eps_infeas = s->eps_infeasible;
     return ds;
 }
 
@@ -797,15 +910,31 @@ static int fetch_vec(std::vector<T> &dst, const T *src, int64_t count, int ms) {
     return QP_OK;
 }
 
-static void vector_stats(BatchData *bd, const std::vector<double> &c, const std::vector<double> &b) {
+// Uploads the c and b the iteration runs on (with preconditioning D2 c and D1 b) and
+// the per-instance statistics: infinity norms of the given vectors (relKKT), 2-norms of
+// the iterated ones (initial primal weight).
+static int upload_vectors(BatchData *bd, const std::vector<double> &c, const std::vector<double> &b) {
+    const int64_t n = bd->ntot, m = bd->mtot;
+    std::vector<double> cs(c), bs(b);
+    if (!bd->h_d.empty()) {
+        for (int64_t j = 0; j < n; ++j) cs[j] = c[j] * bd->h_d[j];
+        for (int64_t r = 0; r < m; ++r) bs[r] = b[r] * bd->h_d[n + r];
+    }
+    auto put = [&](DevMem &dm, const std::vector<double> &v) -> int {
+        if (!dm.p) return dm.upload(v.data(), v.size() * 8);
+        if (!v.empty()) HIPCHK(hipMemcpy(dm.p, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+        return QP_OK;
+    };
+    int rc;
+    if ((rc = put(bd->c, cs)) || (rc = put(bd->b, bs))) return rc;
     for (int i = 0; i < bd->B; ++i) {
         double cn = 0.0, ci = 0.0, bn = 0.0, bi = 0.0;
         for (int64_t j = bd->var_off[i]; j < bd->var_off[i + 1]; ++j) {
-            cn += c[j] * c[j];
+            cn += cs[j] * cs[j];
             if (std::fabs(c[j]) > ci) ci = std::fabs(c[j]);
         }
         for (int64_t r = bd->row_off[i]; r < bd->row_off[i + 1]; ++r) {
-            bn += b[r] * b[r];
+            bn += bs[r] * bs[r];
             if (std::fabs(b[r]) > bi) bi = std::fabs(b[r]);
         }
         bd->c_norm2[i] = std::sqrt(cn);
@@ -813,6 +942,7 @@ static void vector_stats(BatchData *bd, const std::vector<double> &c, const std:
         bd->c_inf[i] = ci;
         bd->b_inf[i] = bi;
     }
+    return QP_OK;
 }
 
 int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t stream,
@@ -960,10 +1090,59 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
         (rc = bd->a_val.upload(av.data(), av.size() * 8)) ||
         (rc = bd->p_rowptr.upload(pr.data(), pr.size() * 4)) ||
         (rc = bd->p_col.upload(pc.data(), pc.size() * 4)) ||
-        (rc = bd->p_val.upload(pv.data(), pv.size() * 8)) || (rc = bd->c.upload(c.data(), nb)) ||
-        (rc = bd->b.upload(b.data(), b.size() * 8)) || (rc = bd->l.upload(l.data(), nb)) ||
-        (rc = bd->u.upload(u.data(), nb)) || (rc = bd->rt.upload(rt.data(), rt.size())) ||
-        (rc = bd->x.alloc(nb)) || (rc = bd->xbar.alloc(nb)) || (rc = bd->xt.alloc(nb)) ||
+        (rc = bd->p_val.upload(pv.data(), pv.size() * 8)) ||
+        (rc = bd->rt.upload(rt.data(), rt.size()))) {
+        delete bd;
+        return rc;
+    }
+    bd->c_norm2.assign(B, 0.0);
+    bd->b_norm2.assign(B, 0.0);
+    bd->c_inf.assign(B, 0.0);
+    bd->b_inf.assign(B, 0.0);
+    // Sec. 5 preprocessing, per instance (each instance's own K), on the device
+    std::vector<double> ls(l), us(u);
+    if (s->precondition) {
+        DevMem work;
+        if ((rc = work.alloc((size_t)(n + m) * 16)) ||
+            (rc = bd->dscale.alloc((size_t)(n + m) * 8))) {
+            delete bd;
+            return rc;
+        }
+        ScaleInput in{};
+        in.n = n;
+        in.m = m;
+        in.a_rowptr = bd->a_rowptr.as<int32_t>();
+        in.a_col = bd->a_col.as<int32_t>();
+        in.a_val = bd->a_val.as<double>();
+        in.p_rowptr = bd->p_rowptr.as<int32_t>();
+        in.p_col = bd->p_col.as<int32_t>();
+        in.p_val = bd->p_val.as<double>();
+        in.var_off = bd->var_off_d.as<int32_t>();
+        in.row_off = bd->row_off_d.as<int32_t>();
+        in.count = B;
+        in.ruiz_iters = s->ruiz_iters;
+        in.l2 = 1;
+        in.pc = 1;
+        if (precondition_device(stream, in, work.as<double>(), bd->dscale.as<double>())) {
+            delete bd;
+            return fail(QP_ERR_DEVICE, "preconditioning kernels failed to launch");
+        }
+        bd->h_d.resize((size_t)(n + m));
+        if (hipStreamSynchronize(stream) != hipSuccess ||
+            hipMemcpy(bd->h_d.data(), bd->dscale.p, (size_t)(n + m) * 8, hipMemcpyDeviceToHost) !=
+                hipSuccess) {
+            delete bd;
+            return fail(QP_ERR_DEVICE, "preconditioning failed");
+        }
+        for (int64_t j = 0; j < n; ++j) {
+            ls[j] = l[j] / bd->h_d[j];
+            us[j] = u[j] / bd->h_d[j];
+        }
+    }
+    bd->h_c = c;
+    bd->h_b = b;
+    if ((rc = upload_vectors(bd, c, b)) || (rc = bd->l.upload(ls.data(), nb)) ||
+        (rc = bd->u.upload(us.data(), nb)) || (rc = bd->x.alloc(nb)) || (rc = bd->xbar.alloc(nb)) || (rc = bd->xt.alloc(nb)) ||
         (rc = bd->xmd0.alloc(nb)) || (rc = bd->xmd1.alloc(nb)) || (rc = bd->xrs.alloc(nb)) ||
         (rc = bd->y.alloc(mb)) || (rc = bd->ybar.alloc(mb)) || (rc = bd->yrs.alloc(mb)) ||
         (rc = bd->x_out.alloc(nb)) || (rc = bd->y_out.alloc(mb)) || (rc = bd->x0.alloc(nb)) ||
@@ -978,11 +1157,6 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
     }
     bd->normA.assign(B, 0.0);
     bd->normQ.assign(B, 0.0);
-    bd->c_norm2.assign(B, 0.0);
-    bd->b_norm2.assign(B, 0.0);
-    bd->c_inf.assign(B, 0.0);
-    bd->b_inf.assign(B, 0.0);
-    vector_stats(bd, c, b);
     // size classes and queue order (decreasing nonzeros: long instances start first)
     bd->cls.resize(B);
     bd->order.assign(NCLASS, {});
@@ -1086,15 +1260,18 @@ int batch_set_norms(BatchData *b, const double *norm_A, const double *norm_Q) {
     return QP_OK;
 }
 
-int batch_update_vectors(BatchData *bd, const double *c, const double *bvec, int ms) {
-    const hipMemcpyKind kind = ms == QP_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    if (c) HIPCHK(hipMemcpy(bd->c.p, c, (size_t)bd->ntot * 8, kind));
-    if (bvec && bd->mtot) HIPCHK(hipMemcpy(bd->b.p, bvec, (size_t)bd->mtot * 8, kind));
-    std::vector<double> hc(bd->ntot), hb(bd->mtot);
-    HIPCHK(hipMemcpy(hc.data(), bd->c.p, (size_t)bd->ntot * 8, hipMemcpyDeviceToHost));
-    if (bd->mtot) HIPCHK(hipMemcpy(hb.data(), bd->b.p, (size_t)bd->mtot * 8, hipMemcpyDeviceToHost));
-    vector_stats(bd, hc, hb);
+int batch_scaling(BatchData *bd, double *d_var, double *d_row) {
+    const int64_t n = bd->ntot, m = bd->mtot;
+    for (int64_t j = 0; d_var && j < n; ++j) d_var[j] = bd->h_d.empty() ? 1.0 : bd->h_d[j];
+    for (int64_t i = 0; d_row && i < m; ++i) d_row[i] = bd->h_d.empty() ? 1.0 : bd->h_d[n + i];
     return QP_OK;
+}
+
+int batch_update_vectors(BatchData *bd, const double *c, const double *bvec, int ms) {
+    const hipMemcpyKind kind = ms == QP_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
+    if (c) HIPCHK(hipMemcpy(bd->h_c.data(), c, (size_t)bd->ntot * 8, kind));
+    if (bvec && bd->mtot) HIPCHK(hipMemcpy(bd->h_b.data(), bvec, (size_t)bd->mtot * 8, kind));
+    return upload_vectors(bd, bd->h_c, bd->h_b);
 }
 
 int batch_set_threads(BatchData *b, const int32_t *threads) {
@@ -1140,6 +1317,12 @@ static int run_batch(BatchData *bd, const qp_settings *s, int ms, const qp_warm_
             any_warm = true;
         }
     }
+    if (any_warm && !bd->h_d.empty()) {  // warm starts refer to the given problem
+        launch_scale_pair(st, bd->x0.as<double>(), bd->x0.as<double>(), bd->dscale.as<double>(),
+                          bd->ntot, 1);
+        launch_scale_pair(st, bd->y0.as<double>(), bd->y0.as<double>(),
+                          bd->dscale.as<double>() + bd->ntot, bd->mtot, 1);
+    }
     HIPCHK(hipMemcpyAsync(bd->omega0_d.p, omega.data(), (size_t)B * 8, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(bd->has_x0.p, hx.data(), (size_t)B, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(bd->has_y0.p, hy.data(), (size_t)B, hipMemcpyHostToDevice, st));
@@ -1174,6 +1357,13 @@ int batch_solve(BatchData *bd, const qp_settings *s, int ms, const qp_warm_start
     std::vector<State> S(bd->B);
     HIPCHK(hipMemcpy(S.data(), bd->res.p, (size_t)bd->B * sizeof(State), hipMemcpyDeviceToHost));
     const hipMemcpyKind kind = ms == QP_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (!bd->h_d.empty()) {  // back to the given problem: x = D2 x~, y = D1 y~
+        launch_scale_pair(bd->stream, bd->x_out.as<double>(), bd->x_out.as<double>(),
+                          bd->dscale.as<double>(), bd->ntot, 0);
+        launch_scale_pair(bd->stream, bd->y_out.as<double>(), bd->y_out.as<double>(),
+                          bd->dscale.as<double>() + bd->ntot, bd->mtot, 0);
+        HIPCHK(hipStreamSynchronize(bd->stream));
+    }
     if (x_out) HIPCHK(hipMemcpy(x_out, bd->x_out.p, (size_t)bd->ntot * 8, kind));
     if (y_out && bd->mtot) HIPCHK(hipMemcpy(y_out, bd->y_out.p, (size_t)bd->mtot * 8, kind));
     for (int i = 0; i < bd->B; ++i) {

@@ -99,6 +99,20 @@ __device__ __forceinline__ void rel_kkt_point(const double *ra, const double *rp
     out[5] = D;
 }
 
+// Infeasibility certificates from S.inf (the paper is silent; the quantities are those
+// of the drift z - z_restart, projected): primal infeasible when the dual direction is a
+// Farkas ray, max |A'dy+| over unbounded components <= tol (b'dy+ - support), with
+// b'dy+ - support > 0; dual infeasible when the primal direction descends without
+// bound, max(||Q dx+||, A dx+ violation) <= tol (-c'dx+), with c'dx+ < 0.
+__device__ __forceinline__ int infeas_status(const State &S, const DevSettings &s) {
+    const double farkas = S.inf[INF_BDY] - S.inf[INF_SUPP];
+    if (farkas > 0.0 && S.inf[INF_GVIOL] / farkas <= s.eps_infeas) return ST_PRIMAL_INFEASIBLE;
+    const double cdx = S.inf[INF_CDX];
+    const double dviol = fmax(S.inf[INF_QDX], S.inf[INF_AVIOL]);
+    if (cdx < 0.0 && dviol / -cdx <= s.eps_infeas) return ST_DUAL_INFEASIBLE;
+    return -1;
+}
+
 // One evaluation (DECIDE_INIT / DECIDE_CHECK / DECIDE_FALLBACK) applied to S.
 // Returns the restart flag (the caller copies the candidate if set).
 __device__ __forceinline__ int decide_update(int mode, const double *ra, const double *rp,
@@ -147,6 +161,9 @@ __device__ __forceinline__ int decide_update(int mode, const double *ra, const d
             S.done = 1;
         } else if (rc <= s.eps) {
             S.status = ST_OPTIMAL;
+            S.done = 1;
+        } else if (s.detect_infeas && infeas_status(S, s) >= 0) {
+            S.status = infeas_status(S, s);
             S.done = 1;
         } else if (S.total >= s.max_iter) {
             S.status = ST_ITER_LIMIT;

@@ -90,10 +90,20 @@ enum : int {
     RP_BND0, RP_BND1, RP_DX0, RP_DX1, RP_NV
 };
 
+// Infeasibility certificate quantities of the direction (dx+, dy+) = projected
+// z - z_restart, on the given problem: max violation of A dx+ (EQ |.|, GE [-.]+),
+// b'dy+, ||Q dx+||_inf, max |A'dy+| over components whose needed bound is infinite,
+// the support of X along A'dy+ over finite bounds, c'dx+.
+enum : int { INF_AVIOL = 0, INF_BDY, INF_QDX, INF_GVIOL, INF_SUPP, INF_CDX, INF_NV };
+// per-block partials: rows of A (maxima first) and rows of P (maxima first)
+enum : int { IA_AVIOL = 0, IA_BDY, IA_NV };
+enum : int { IP_QDX = 0, IP_GVIOL, IP_SUPP, IP_CDX, IP_NV };
+
 struct State {
     double omega, r0, prev_cand, s_last;
     double r_cur, r_avg;
     double kkt[2][6];  // per point: r_primal, r_dual, r_gap, rel_kkt, primal_obj, dual_obj
+    double inf[INF_NV];  // infeasibility quantities of the last evaluation
     int64_t total, k, restarts, kkt_evals;
     int32_t done, status, cand, restart_flag;
     int32_t used_warm, checks, pad0, pad1;
@@ -105,11 +115,14 @@ struct DevSettings {
     int64_t max_iter;
     int32_t restart_mode, fixed_K, interval;
     int32_t momentum;  // 1: Algorithm 1 weights; 0: plain PDHG (beta = theta = 1)
+    int32_t detect_infeas;
+    double eps_infeas;
 };
 
 enum : int { DECIDE_INIT = 0, DECIDE_CHECK = 1, DECIDE_FALLBACK = 2 };
 enum : int { MODE_ADAPTIVE = 0, MODE_FIXED_K = 1, MODE_HALVING = 2, MODE_NONE = 3 };
-enum : int { ST_OPTIMAL = 0, ST_ITER_LIMIT = 1, ST_TIME_LIMIT = 2, ST_NUMERICAL = 3 };
+enum : int { ST_OPTIMAL = 0, ST_ITER_LIMIT = 1, ST_TIME_LIMIT = 2, ST_NUMERICAL = 3,
+             ST_PRIMAL_INFEASIBLE = 4, ST_DUAL_INFEASIBLE = 5 };
 
 // Vectors of a single-instance solve (device pointers).
 struct Vecs {
@@ -118,7 +131,16 @@ struct Vecs {
     double *y, *ybar, *yrs;               // dual
     const double *c, *b, *l, *u;
     const uint8_t *rt;
+    const double *dv, *dr;                // preconditioning D2 [n], D1 [m], or nullptr
 };
+
+// ---- infeasibility certificates (qp_kernels.hip) ----
+// dxh [n], dyh [m]: scratch for the projected directions; part_a / part_p: per-block
+// partials with FOLD_SLOTS spare slots; writes st->inf.
+void launch_infeas(hipStream_t s, const Blocks &bkA, const Csr &A, const Blocks &bkP,
+                   const Csr &P, const Vecs &v, double *dxh, double *dyh, double *part_a,
+                   int32_t nslotA, double *part_p, int32_t nslotP, State *st, int64_t n,
+                   int64_t m);
 
 // ---- diagonal preconditioning (qp_scale.hip) ----
 enum : int { SCALE_MAX = 0, SCALE_L2 = 1, SCALE_SUM = 2 };
@@ -128,15 +150,13 @@ struct ScaleInput {
     double *a_val;                      // scaled in place
     const int32_t *p_rowptr, *p_col;    // device CSR of P = [Q | -A']
     double *p_val;                      // scaled in place
-    const int64_t *var_off, *row_off;   // device batch offsets [count+1], or nullptr
+    const int32_t *var_off, *row_off;   // device batch offsets [count+1], or nullptr
     int32_t count;
     int32_t ruiz_iters, l2, pc;
 };
 // d (device, n+m): receives the cumulative scaling (D2 for variables, then D1);
 // work: 2(n+m) doubles.
 int precondition_device(hipStream_t s, const ScaleInput &in, double *work, double *d);
-void launch_gather_values(hipStream_t s, double *dst, const double *src, const int32_t *idx,
-                          int64_t len);
 // out = in * d (divide = 0) or in / d (divide = 1), elementwise
 void launch_scale_pair(hipStream_t s, double *out, const double *in, const double *d,
                        int64_t len, int divide);

@@ -81,6 +81,19 @@ __device__ double block_sum_lds(const double *prod, int cnt, double *scratch) {
     return t;  // valid in thread 0
 }
 
+// Deterministic block sum of one value per thread (valid in thread 0).
+__device__ double block_sum_value(double s, double *scratch) {
+    s = wave_sum(s);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) scratch[wid] = s;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < BS / 64; ++w) t = t + scratch[w];
+    __syncthreads();
+    return t;
+}
+
 // Chunk partial sums of a long row: thread 0 publishes its W partial sums;
 // the last chunk to arrive (atomic counter) adds all partials in chunk order.
 // Returns true in thread 0 of the last block, with the row totals in tot[].
@@ -254,6 +267,7 @@ __global__ __launch_bounds__(BS) void k_primal(Blocks bk, Csr P, PrimalArgs a,
 struct KktRowArgs {
     const double *x, *xbar, *y, *ybar, *yrs, *b;
     const uint8_t *rt;
+    const double *dr;  // row scaling D1 of a preconditioned problem, or nullptr
     double *partials;  // [(nblk + nlr) * RA_NV]
 };
 
@@ -266,10 +280,13 @@ __device__ __forceinline__ void kkt_row_contrib(int i, double s0, double s1, con
         r0 = (r0 < 0.0) ? -r0 : 0.0;
         r1 = (r1 < 0.0) ? -r1 : 0.0;
     }
-    cv[RA_RES0] = fabs(r0);
-    cv[RA_RES1] = fabs(r1);
-    cv[RA_AX0] = fabs(s0);
-    cv[RA_AX1] = fabs(s1);
+    // preconditioned: the original problem's row i is row i of the scaled one divided
+    // by D1_i (relKKT is measured on the given problem; dot products are invariant)
+    const double sr = a.dr ? a.dr[i] : 1.0;
+    cv[RA_RES0] = fabs(r0) / sr;
+    cv[RA_RES1] = fabs(r1) / sr;
+    cv[RA_AX0] = fabs(s0) / sr;
+    cv[RA_AX1] = fabs(s1) / sr;
     const double yi = a.y[i], ybi = a.ybar[i], yr = a.yrs[i];
     cv[RA_BY0] = bi * yi;
     cv[RA_BY1] = bi * ybi;
@@ -363,6 +380,7 @@ __global__ __launch_bounds__(BS) void k_kkt_rows(Blocks bk, Csr A, KktRowArgs a,
 // ---------------------------------------------------------------------------
 struct KktColArgs {
     const double *x, *xbar, *y, *ybar, *xrs, *c, *l, *u;
+    const double *dv;  // column scaling D2 of a preconditioned problem, or nullptr
     double *partials;  // [(nblk + nlr) * RP_NV]
 };
 
@@ -370,6 +388,7 @@ __device__ __forceinline__ void kkt_col_contrib(int j, const double *qx, const d
                                                 const KktColArgs &a, double *cv) {
     const double cj = a.c[j], lj = a.l[j], uj = a.u[j];
     const bool lo_fin = isfinite(lj), hi_fin = isfinite(uj);
+    const double sv = a.dv ? a.dv[j] : 1.0;  // original column j = scaled one / D2_j
     for (int p = 0; p < 2; ++p) {
         const double xp = p == 0 ? a.x[j] : a.xbar[j];
         const double aty = -naty[p];
@@ -379,9 +398,9 @@ __device__ __forceinline__ void kkt_col_contrib(int j, const double *qx, const d
         else if (lo_fin) lam_hat = lam > 0.0 ? lam : 0.0;
         else if (hi_fin) lam_hat = lam < 0.0 ? lam : 0.0;
         else lam_hat = 0.0;
-        cv[RP_DRES0 + p] = fabs(lam - lam_hat);
-        cv[RP_QX0 + p] = fabs(qx[p]);
-        cv[RP_ATY0 + p] = fabs(aty);
+        cv[RP_DRES0 + p] = fabs(lam - lam_hat) / sv;
+        cv[RP_QX0 + p] = fabs(qx[p]) / sv;
+        cv[RP_ATY0 + p] = fabs(aty) / sv;
         cv[RP_XQX0 + p] = xp * qx[p];
         cv[RP_CX0 + p] = cj * xp;
         double bnd = 0.0;
@@ -568,6 +587,213 @@ __global__ __launch_bounds__(BS) void k_decide(int mode, const double *__restric
         S.s_last = sl;
     }
     *st = S;
+}
+
+// ---------------------------------------------------------------------------
+// infeasibility certificates (the paper is silent; see the decision in
+// qp_decide.h): the drift z - z_restart, projected onto the dual cone (dy+) and
+// onto the recession cone of X (dx+), and the products A dx+, Q dx+, A'dy+
+// ---------------------------------------------------------------------------
+__global__ void k_infeas_dirs(const double *__restrict__ x, const double *__restrict__ xrs,
+                              const double *__restrict__ l, const double *__restrict__ u,
+                              const double *__restrict__ y, const double *__restrict__ yrs,
+                              const uint8_t *__restrict__ rt, double *__restrict__ dxh,
+                              double *__restrict__ dyh, int64_t n, int64_t m,
+                              const State *__restrict__ st) {
+    if (st->done) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const bool lo = isfinite(l[k]), hi = isfinite(u[k]);
+        double v = x[k] - xrs[k];
+        if (lo && hi) v = 0.0;
+        else if (lo && v < 0.0) v = 0.0;
+        else if (hi && v > 0.0) v = 0.0;
+        dxh[k] = v;
+    }
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += stride) {
+        const double v = y[k] - yrs[k];
+        dyh[k] = (rt[k] == 1 && v < 0.0) ? 0.0 : v;
+    }
+}
+
+struct InfRowArgs {
+    const double *dxh, *dyh, *b, *dr;
+    const uint8_t *rt;
+    double *partials;  // [(nblk + nlr) * IA_NV]
+};
+
+__device__ __forceinline__ void infeas_row_contrib(int i, double s, const InfRowArgs &a,
+                                                   double *cv) {
+    const double viol = a.rt[i] == 1 ? (s < 0.0 ? -s : 0.0) : fabs(s);
+    cv[IA_AVIOL] = viol / (a.dr ? a.dr[i] : 1.0);
+    cv[IA_BDY] = a.b[i] * a.dyh[i];
+}
+
+__global__ __launch_bounds__(BS) void k_infeas_rows(Blocks bk, Csr A, InfRowArgs a,
+                                                    const State *__restrict__ st) {
+    if (st->done) return;
+    __shared__ double prod[NNZ_BLK];
+    __shared__ double scratch[BS / 64];
+    const int bi = xcd_block(blockIdx.x, gridDim.x);
+    const Block B = bk.blk[bi];
+    const int t = threadIdx.x;
+    {
+        int cols[EPT];
+        double vals[EPT], g[EPT];
+        load_block(A.col, A.val, B.e0, B.e1, t, cols, vals);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) g[i] = a.dxh[cols[i]];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) prod[i * BS + t] = vals[i] * g[i];
+    }
+    __syncthreads();
+    double cv[IA_NV] = {0.0, 0.0};
+    const int lr = bk.lr[bi];
+    if (lr < 0) {
+        const int nrows = B.row1 - B.row0;
+        const int G = lanes_per_row(nrows);
+        const int rl = t / G, lane = t % G;
+        double sum = 0.0;
+        if (rl < nrows) {
+            const int row = B.row0 + rl;
+            const int e1 = A.rowptr[row + 1] - B.e0;
+            for (int e = A.rowptr[row] - B.e0 + lane; e < e1; e += G) sum = sum + prod[e];
+        }
+        sum = group_sum(sum, G);
+        if (rl < nrows && lane == 0) infeas_row_contrib(B.row0 + rl, sum, a, cv);
+        block_reduce_write<IA_NV, 1>(cv, a.partials + (size_t)bi * IA_NV);
+    } else {
+        const double part = block_sum_lds(prod, B.e1 - B.e0, scratch);
+        if (t == 0)
+            for (int v = 0; v < IA_NV; ++v) a.partials[(size_t)bi * IA_NV + v] = 0.0;
+        double tot;
+        if (chunk_finish<1>(bk, bi, lr, &part, &tot)) {
+            infeas_row_contrib(B.row0, tot, a, cv);
+            for (int v = 0; v < IA_NV; ++v)
+                a.partials[(size_t)(bk.nblk + lr) * IA_NV + v] = cv[v];
+        }
+    }
+}
+
+struct InfColArgs {
+    const double *dxh, *dyh, *c, *l, *u, *dv;
+    double *partials;  // [(nblk + nlr) * IP_NV]
+};
+
+// qd = (Q dx+)_j, nat = (-A'dy+)_j (P stores -A')
+__device__ __forceinline__ void infeas_col_contrib(int j, double qd, double nat,
+                                                   const InfColArgs &a, double *cv) {
+    const double sv = a.dv ? a.dv[j] : 1.0;
+    const double g = -nat;
+    const double lj = a.l[j], uj = a.u[j];
+    double viol = 0.0, supp = 0.0;
+    if (g > 0.0) {
+        if (isfinite(uj)) supp = uj * g;
+        else viol = g;
+    } else if (g < 0.0) {
+        if (isfinite(lj)) supp = lj * g;
+        else viol = -g;
+    }
+    cv[IP_QDX] = fabs(qd) / sv;
+    cv[IP_GVIOL] = viol / sv;
+    cv[IP_SUPP] = supp;
+    cv[IP_CDX] = a.c[j] * a.dxh[j];
+}
+
+__global__ __launch_bounds__(BS) void k_infeas_cols(Blocks bk, Csr P, InfColArgs a,
+                                                    const State *__restrict__ st, int32_t n) {
+    if (st->done) return;
+    __shared__ double prod[NNZ_BLK];
+    __shared__ uint8_t isA[NNZ_BLK];
+    __shared__ double scratch[BS / 64];
+    const int bi = xcd_block(blockIdx.x, gridDim.x);
+    const Block B = bk.blk[bi];
+    const int t = threadIdx.x;
+    {
+        int cols[EPT];
+        double vals[EPT], g[EPT];
+        load_block(P.col, P.val, B.e0, B.e1, t, cols, vals);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int cc = cols[i];
+            g[i] = *(cc >= n ? a.dyh + (cc - n) : a.dxh + cc);
+        }
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            prod[i * BS + t] = vals[i] * g[i];
+            isA[i * BS + t] = cols[i] >= n;
+        }
+    }
+    __syncthreads();
+    double cv[IP_NV] = {0.0, 0.0, 0.0, 0.0};
+    const int lr = bk.lr[bi];
+    if (lr < 0) {
+        const int nrows = B.row1 - B.row0;
+        const int G = lanes_per_row(nrows);
+        const int rl = t / G, lane = t % G;
+        double q = 0.0, na = 0.0;
+        if (rl < nrows) {
+            const int row = B.row0 + rl;
+            const int e1 = P.rowptr[row + 1] - B.e0;
+            for (int e = P.rowptr[row] - B.e0 + lane; e < e1; e += G) {
+                if (isA[e]) na = na + prod[e];
+                else q = q + prod[e];
+            }
+        }
+        q = group_sum(q, G);
+        na = group_sum(na, G);
+        if (rl < nrows && lane == 0) infeas_col_contrib(B.row0 + rl, q, na, a, cv);
+        block_reduce_write<IP_NV, 2>(cv, a.partials + (size_t)bi * IP_NV);
+    } else {
+        // long row: the chunk's Q and -A' products summed separately
+        double part[2];
+        double qs = 0.0, as = 0.0;
+        for (int k = t; k < B.e1 - B.e0; k += BS) {
+            if (isA[k]) as = as + prod[k];
+            else qs = qs + prod[k];
+        }
+        part[0] = block_sum_value(qs, scratch);
+        part[1] = block_sum_value(as, scratch);
+        if (t == 0)
+            for (int v = 0; v < IP_NV; ++v) a.partials[(size_t)bi * IP_NV + v] = 0.0;
+        double tot[2];
+        if (chunk_finish<2>(bk, bi, lr, part, tot)) {
+            infeas_col_contrib(B.row0, tot[0], tot[1], a, cv);
+            for (int v = 0; v < IP_NV; ++v)
+                a.partials[(size_t)(bk.nblk + lr) * IP_NV + v] = cv[v];
+        }
+    }
+}
+
+// folds the (already folded) per-block partials of both kernels into st->inf
+__global__ __launch_bounds__(BS) void k_infeas_final(const double *__restrict__ pa, int32_t na,
+                                                     const double *__restrict__ pp, int32_t np,
+                                                     State *st) {
+    if (st->done) return;
+    __shared__ double red[INF_NV][BS];
+    const int t = threadIdx.x;
+    double acc[INF_NV] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = t; i < na; i += BS) {
+        acc[INF_AVIOL] = nmax(acc[INF_AVIOL], pa[(size_t)i * IA_NV + IA_AVIOL]);
+        acc[INF_BDY] = acc[INF_BDY] + pa[(size_t)i * IA_NV + IA_BDY];
+    }
+    for (int i = t; i < np; i += BS) {
+        acc[INF_QDX] = nmax(acc[INF_QDX], pp[(size_t)i * IP_NV + IP_QDX]);
+        acc[INF_GVIOL] = nmax(acc[INF_GVIOL], pp[(size_t)i * IP_NV + IP_GVIOL]);
+        acc[INF_SUPP] = acc[INF_SUPP] + pp[(size_t)i * IP_NV + IP_SUPP];
+        acc[INF_CDX] = acc[INF_CDX] + pp[(size_t)i * IP_NV + IP_CDX];
+    }
+    for (int v = 0; v < INF_NV; ++v) red[v][t] = acc[v];
+    __syncthreads();
+    for (int h = BS / 2; h >= 1; h >>= 1) {
+        if (t < h)
+            for (int v = 0; v < INF_NV; ++v) {
+                const bool mx = v == INF_AVIOL || v == INF_QDX || v == INF_GVIOL;
+                red[v][t] = mx ? nmax(red[v][t], red[v][t + h]) : red[v][t] + red[v][t + h];
+            }
+        __syncthreads();
+    }
+    if (t < INF_NV) st->inf[t] = red[t][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -799,6 +1025,7 @@ void launch_kkt_rows(hipStream_t s, const Blocks &bk, const Csr &A, const Vecs &
     a.yrs = v.yrs;
     a.b = v.b;
     a.rt = v.rt;
+    a.dr = v.dr;
     a.partials = partials;
     hipLaunchKernelGGL(k_kkt_rows, dim3(bk.nblk), dim3(BS), 0, s, bk, A, a, st);
 }
@@ -815,8 +1042,58 @@ void launch_kkt_cols(hipStream_t s, const Blocks &bk, const Csr &P, const Vecs &
     a.c = v.c;
     a.l = v.l;
     a.u = v.u;
+    a.dv = v.dv;
     a.partials = partials;
     hipLaunchKernelGGL(k_kkt_cols, dim3(bk.nblk), dim3(BS), 0, s, bk, P, a, st, (int32_t)n);
+}
+
+void launch_infeas(hipStream_t s, const Blocks &bkA, const Csr &A, const Blocks &bkP,
+                   const Csr &P, const Vecs &v, double *dxh, double *dyh, double *part_a,
+                   int32_t nslotA, double *part_p, int32_t nslotP, State *st, int64_t n,
+                   int64_t m) {
+    hipLaunchKernelGGL(k_infeas_dirs, dim3(grid_for(n > m ? n : m)), dim3(256), 0, s, v.x, v.xrs,
+                       v.l, v.u, v.y, v.yrs, v.rt, dxh, dyh, n, m, st);
+    if (bkA.nblk > 0) {
+        InfRowArgs a;
+        a.dxh = dxh;
+        a.dyh = dyh;
+        a.b = v.b;
+        a.dr = v.dr;
+        a.rt = v.rt;
+        a.partials = part_a;
+        hipLaunchKernelGGL(k_infeas_rows, dim3(bkA.nblk), dim3(BS), 0, s, bkA, A, a, st);
+    }
+    if (bkP.nblk > 0) {
+        InfColArgs a;
+        a.dxh = dxh;
+        a.dyh = dyh;
+        a.c = v.c;
+        a.l = v.l;
+        a.u = v.u;
+        a.dv = v.dv;
+        a.partials = part_p;
+        hipLaunchKernelGGL(k_infeas_cols, dim3(bkP.nblk), dim3(BS), 0, s, bkP, P, a, st,
+                           (int32_t)n);
+    }
+    // fold many block partials first (same scheme as the KKT reduction)
+    auto fold = [&](double *part, int32_t nslot, int nv) -> int32_t {
+        if (nslot <= 2 * BS) return nslot;
+        const int32_t per = std::max<int32_t>(2 * BS, (nslot + FOLD_SLOTS - 1) / FOLD_SLOTS);
+        const int32_t g = (nslot + per - 1) / per;
+        double *out = part + (size_t)nslot * nv;
+        if (nv == IA_NV)
+            hipLaunchKernelGGL((k_fold_slots<IA_NV, 1>), dim3(g), dim3(BS), 0, s, part, nslot,
+                               per, out, st);
+        else
+            hipLaunchKernelGGL((k_fold_slots<IP_NV, 2>), dim3(g), dim3(BS), 0, s, part, nslot,
+                               per, out, st);
+        return -g;
+    };
+    const int32_t fa = fold(part_a, nslotA, IA_NV), fp = fold(part_p, nslotP, IP_NV);
+    const double *pa = fa < 0 ? part_a + (size_t)nslotA * IA_NV : part_a;
+    const double *pp = fp < 0 ? part_p + (size_t)nslotP * IP_NV : part_p;
+    hipLaunchKernelGGL(k_infeas_final, dim3(1), dim3(BS), 0, s, pa, fa < 0 ? -fa : fa, pp,
+                       fp < 0 ? -fp : fp, st);
 }
 
 // The partial buffers hold FOLD_SLOTS spare slots after the nslot block partials: many

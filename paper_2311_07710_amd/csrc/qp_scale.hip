@@ -28,13 +28,13 @@ struct ScaleView {
     double *a_val;
     const int32_t *p_rowptr, *p_col;       // P = [Q | -A']: n rows
     double *p_val;
-    const int64_t *var_off, *row_off;      // batch offsets [count+1] or nullptr
+    const int32_t *var_off, *row_off;      // batch offsets [count+1] or nullptr
     int32_t count;
     double *st, *f, *d;                    // [n+m] statistic, step factor, cumulative scale
 };
 
 // instance of a global index (offsets off[0..count], increasing)
-__device__ __forceinline__ int find_instance(const int64_t *off, int32_t count, int64_t g) {
+__device__ __forceinline__ int find_instance(const int32_t *off, int32_t count, int64_t g) {
     int lo = 0, hi = count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -99,12 +99,6 @@ __global__ void k_fill_one(double *d, int64_t len) {
     if (r < len) d[r] = 1.0;
 }
 
-__global__ void k_gather_values(double *__restrict__ dst, const double *__restrict__ src,
-                                const int32_t *__restrict__ idx, int64_t len) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < len) dst[e] = src[idx[e]];
-}
-
 __global__ void k_scale_pair(double *__restrict__ out, const double *__restrict__ in,
                              const double *__restrict__ d, int64_t len, int divide) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -142,13 +136,6 @@ int precondition_device(hipStream_t s, const ScaleInput &in, double *work, doubl
     if (in.l2) step(SCALE_L2);
     if (in.pc) step(SCALE_SUM);
     return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-void launch_gather_values(hipStream_t s, double *dst, const double *src, const int32_t *idx,
-                          int64_t len) {
-    if (len > 0)
-        hipLaunchKernelGGL(k_gather_values, dim3(grid_of(len)), dim3(256), 0, s, dst, src, idx,
-                           len);
 }
 
 void launch_scale_pair(hipStream_t s, double *out, const double *in, const double *d,

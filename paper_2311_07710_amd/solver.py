@@ -41,6 +41,10 @@ class Settings:
     panels_dual: int = 0
     panels_primal: int = 0
     momentum: int = 1
+    precondition: int = 0
+    ruiz_iters: int = 10
+    detect_infeasibility: int = 0
+    eps_infeasible: float = 1e-8
 
     def c_struct(self) -> B.qp_settings:
         s = B.qp_settings()
@@ -143,6 +147,12 @@ class Solver:
         B.check(self.lib.qp_get_norms(self.h, C.addressof(a), C.addressof(q)))
         return a.value, q.value
 
+    def scaling(self):
+        """(D2, D1) of the Sec. 5 preprocessing (ones when it is off)."""
+        dv, dr = np.zeros(self.n), np.zeros(max(self.m, 1))
+        B.check(self.lib.qp_get_scaling(self.h, dv.ctypes.data, dr.ctypes.data))
+        return dv, dr[:self.m]
+
     def set_norms(self, norm_A: float, norm_Q: float):
         a, q = C.c_double(norm_A), C.c_double(norm_Q)
         B.check(self.lib.qp_set_norms(self.h, C.byref(a), C.byref(q)))
@@ -224,6 +234,13 @@ class BatchSolver:
         q = np.zeros(self.count)
         B.check(self.lib.qp_get_norms(self.h, a.ctypes.data, q.ctypes.data))
         return a, q
+
+    def scaling(self):
+        """(D2, D1) of the Sec. 5 preprocessing, all instances concatenated."""
+        ntot, mtot = int(self.var_off[-1]), int(self.row_off[-1])
+        dv, dr = np.zeros(max(ntot, 1)), np.zeros(max(mtot, 1))
+        B.check(self.lib.qp_get_scaling(self.h, dv.ctypes.data, dr.ctypes.data))
+        return dv[:ntot], dr[:mtot]
 
     def set_norms(self, norm_A=None, norm_Q=None):
         a = None if norm_A is None else np.ascontiguousarray(norm_A, dtype=np.float64)

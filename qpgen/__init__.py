@@ -20,4 +20,10 @@ from .instances import (  # noqa: F401
     portfolio_family,
     concat_batch,
     csr_from_dense,
+    eq_qp,
+    lasso_qp,
+    huber_qp,
+    svm_qp,
+    primal_infeasible_qp,
+    dual_infeasible_qp,
 )

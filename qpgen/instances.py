@@ -382,3 +382,151 @@ def concat_batch(insts) -> BatchInstances:
     return BatchInstances(B, var_off, row_off, q_rowptr, cat("q_col"), cat("q_val"),
                           a_rowptr, cat("a_col"), cat("a_val"), cat("c"), cat("b"),
                           cat("l"), cat("u"), cat("row_type"), [q.name for q in insts])
+
+
+# ---------------------------------------------------------------------------
+# Further synthetic classes of the paper's large-scale set (Sec. 6.1 lists random
+# QP, random QP with equality constraints, control, portfolio, Huber regression,
+# Lasso and SVM).  Each is the textbook problem written in the QP form above;
+# the data distributions are our own choices.
+# ---------------------------------------------------------------------------
+def _sprandn(rng, m: int, n: int, density: float) -> sp.csr_matrix:
+    return sp.random(m, n, density=density, format="csr", random_state=rng,
+                     data_rvs=rng.standard_normal)
+
+
+def eq_qp(seed: int = 7, n: int = 2000, nnz_per_row: int = 4) -> QPInstance:
+    """min 1/2 x'Qx + c'x  s.t.  Ax = b:  Q = MM' + 0.01 I, A with m = n/2 rows; M and A
+    have nnz_per_row N(0,1) entries in distinct uniform columns of every row; b = A x0 for
+    a random x0; no bounds."""
+    rng = np.random.default_rng(seed)
+    m = n // 2
+    k = min(nnz_per_row, n)
+
+    def rows_k(nrows):   # exactly k distinct columns per row: no empty row
+        cols = _distinct_cols(rng, nrows, n, k)
+        return sp.csr_matrix((rng.standard_normal(nrows * k), cols.ravel(),
+                              np.arange(0, nrows * k + 1, k)), shape=(nrows, n))
+    M = rows_k(n)
+    Q = sp.csr_matrix(M @ M.T + 0.01 * sp.identity(n))
+    A = rows_k(m)
+    x0 = rng.standard_normal(n)
+    b = A @ x0
+    c = rng.standard_normal(n)
+    return _make(f"eq_qp_n{n}_s{seed}", Q, A, c, b, np.full(n, -np.inf), np.full(n, np.inf),
+                 np.full(m, EQ, np.uint8), {"class": "eq_qp"})
+
+
+def lasso_qp(seed: int = 8, n_features: int = 500, m_samples: int = 5000,
+             density: float = 0.05) -> QPInstance:
+    """Lasso  min 1/2 ||Fx - g||^2 + lam ||x||_1  as a QP in z = (x, y, t):
+    min 1/2 y'y + lam 1't  s.t.  Fx - y = g (EQ),  t - x >= 0,  t + x >= 0 (GE).
+    F sparse N(0,1); g = F v + noise with v half zeros; lam = ||F'g||_inf / 5."""
+    rng = np.random.default_rng(seed)
+    n, m = n_features, m_samples
+    F = _sprandn(rng, m, n, density)
+    v = np.where(rng.random(n) < 0.5, rng.standard_normal(n) / np.sqrt(n), 0.0)
+    g = F @ v + rng.standard_normal(m)
+    lam = float(np.abs(F.T @ g).max()) / 5.0
+    N = n + m + n
+    Q = sp.diags(np.concatenate([np.zeros(n), np.ones(m), np.zeros(n)])).tocsr()
+    I_n = sp.identity(n, format="csr")
+    A = sp.vstack([sp.hstack([F, -sp.identity(m), sp.csr_matrix((m, n))]),
+                   sp.hstack([-I_n, sp.csr_matrix((n, m)), I_n]),
+                   sp.hstack([I_n, sp.csr_matrix((n, m)), I_n])]).tocsr()
+    b = np.concatenate([g, np.zeros(2 * n)])
+    c = np.concatenate([np.zeros(n + m), np.full(n, lam)])
+    rt = np.concatenate([np.full(m, EQ), np.full(2 * n, GE)]).astype(np.uint8)
+    return _make(f"lasso_n{n}_m{m}_s{seed}", Q, A, c, b, np.full(N, -np.inf),
+                 np.full(N, np.inf), rt,
+                 {"class": "lasso", "F": F, "g": g, "lam": lam, "n_features": n})
+
+
+def huber_qp(seed: int = 9, n_features: int = 500, m_samples: int = 5000,
+             density: float = 0.05, outlier_frac: float = 0.05) -> QPInstance:
+    """Huber fitting  min sum_i phi(f_i'x - g_i),  phi(s) = s^2 (|s| <= 1), 2|s| - 1
+    (otherwise), as a QP in z = (x, u, r, s):  min u'u + 2 1'(r + s)  s.t.
+    Fx - u - r + s = g (EQ),  r, s >= 0.  g = F v + noise with a few large outliers."""
+    rng = np.random.default_rng(seed)
+    n, m = n_features, m_samples
+    F = _sprandn(rng, m, n, density)
+    v = rng.standard_normal(n) / np.sqrt(n)
+    noise = np.where(rng.random(m) < outlier_frac, 10.0 * rng.standard_normal(m),
+                     0.5 * rng.standard_normal(m))
+    g = F @ v + noise
+    N = n + 3 * m
+    Q = sp.diags(np.concatenate([np.zeros(n), np.full(m, 2.0), np.zeros(2 * m)])).tocsr()
+    I_m = sp.identity(m, format="csr")
+    A = sp.hstack([F, -I_m, -I_m, I_m]).tocsr()
+    c = np.concatenate([np.zeros(n + m), np.full(2 * m, 2.0)])
+    l = np.concatenate([np.full(n + m, -np.inf), np.zeros(2 * m)])
+    return _make(f"huber_n{n}_m{m}_s{seed}", Q, A, c, g, l, np.full(N, np.inf),
+                 np.full(m, EQ, np.uint8),
+                 {"class": "huber", "F": F, "g": g, "n_features": n})
+
+
+def svm_qp(seed: int = 10, n_features: int = 500, m_samples: int = 5000,
+           density: float = 0.05, lam: float = 1.0) -> QPInstance:
+    """Soft-margin SVM  min x'x + lam sum_i max(0, 1 - g_i f_i'x)  as a QP in
+    z = (x, t):  min x'x + lam 1't  s.t.  t_i + g_i f_i'x >= 1 (GE),  t >= 0.
+    Labels g = +1 for the first half of the samples, -1 for the rest; a sample's
+    nonzero features are N(+-1/n, 1/n) by class."""
+    rng = np.random.default_rng(seed)
+    n, m = n_features, m_samples
+    F = _sprandn(rng, m, n, density).tocoo()
+    lab = np.where(np.arange(m) < m // 2, 1.0, -1.0)
+    F.data = (lab[F.row] + rng.standard_normal(F.data.size)) / n
+    F = F.tocsr()
+    N = n + m
+    Q = sp.diags(np.concatenate([np.full(n, 2.0), np.zeros(m)])).tocsr()
+    A = sp.hstack([sp.diags(lab) @ F, sp.identity(m)]).tocsr()
+    c = np.concatenate([np.zeros(n), np.full(m, lam)])
+    l = np.concatenate([np.full(n, -np.inf), np.zeros(m)])
+    return _make(f"svm_n{n}_m{m}_s{seed}", Q, A, c, np.ones(m), l, np.full(N, np.inf),
+                 np.full(m, GE, np.uint8),
+                 {"class": "svm", "F": F, "labels": lab, "lam": lam, "n_features": n})
+
+
+# ---------------------------------------------------------------------------
+# Infeasible and unbounded variants (inputs for infeasibility detection).
+# ---------------------------------------------------------------------------
+def primal_infeasible_qp(seed: int = 1, n: int = 100, m: int = 50) -> QPInstance:
+    """The tiny random QP plus two contradictory rows a'x >= 1 and -a'x >= 0 for a dense
+    random a: y = (1, 1) on them is a Farkas certificate (A'y = 0, b'y = 1)."""
+    base = tiny_random_qp(seed, n=n, m=m)
+    rng = np.random.default_rng([seed, 77])
+    a = rng.standard_normal(n)
+    A = sp.vstack([base.A(), sp.csr_matrix(a[None, :]), sp.csr_matrix(-a[None, :])]).tocsr()
+    b = np.concatenate([base.b, [1.0, 0.0]])
+    rt = np.concatenate([base.row_type, [GE, GE]]).astype(np.uint8)
+    return _make(f"primal_infeasible_s{seed}", base.Q(), A, base.c, b, base.l, base.u, rt,
+                 {"class": "primal_infeasible"})
+
+
+def dual_infeasible_qp(seed: int = 1, n: int = 100, m: int = 50) -> QPInstance:
+    """A feasible QP that is unbounded below along d = -e_0: Q has no curvature along
+    variable 0 (its row and column are zero), x_0 has no lower bound, c_0 = 1, and
+    column 0 of A is 0 on equality rows and <= 0 on >= rows (so A d >= 0)."""
+    base = tiny_random_qp(seed, n=n, m=m)
+    Q = base.Q().tolil()
+    Q[0, :] = 0.0
+    Q[:, 0] = 0.0
+    A = base.A().tolil()
+    col0 = A[:, 0].toarray().ravel()
+    eq = base.row_type == EQ
+    col0[eq] = 0.0
+    col0[~eq] = -np.abs(col0[~eq])
+    A[:, 0] = col0[:, None]
+    c = base.c.copy()
+    c[0] = 1.0
+    l, u = base.l.copy(), base.u.copy()
+    l[0], u[0] = -np.inf, np.inf
+    x0 = base.meta["x_feasible"].copy()
+    A = sp.csr_matrix(A)
+    A.eliminate_zeros()
+    b = A @ x0
+    b[~eq] -= np.random.default_rng([seed, 78]).uniform(0.0, 1.0, int((~eq).sum()))
+    Qc = sp.csr_matrix(Q)
+    Qc.eliminate_zeros()
+    return _make(f"dual_infeasible_s{seed}", Qc, A, c, b, l, u, base.row_type,
+                 {"class": "dual_infeasible"})

@@ -43,17 +43,33 @@ def _norms(orc, qp):
 
 def _pair(orc, qpa, qp, *, eps=1e-6, max_iter=200000, check_every=64, mode=0, fixed_K=100,
           x0=None, y0=None, omega0=0.0, warm_fallback=1, use_graph=1, norms=None, log=True,
-          panels=(0, 0), momentum=1):
-    nA, nQ = norms if norms is not None else _norms(orc, qp)
+          panels=(0, 0), momentum=1, precondition=False, scaling_out=None, detect=False):
+    """Oracle and GPU runs of the same instance and settings.  With precondition the
+    oracle solves its own Sec. 5 scaling of qp (relKKT on qp) and the GPU scales on the
+    device; norms are then those of the scaled problem."""
+    if precondition:
+        sc, dv, dr = orc.precondition(qp)
+        nA, nQ = norms if norms is not None else _norms(orc, sc)
+    else:
+        nA, nQ = norms if norms is not None else _norms(orc, qp)
     os_ = orc.OracleSettings(eps=eps, max_iter=max_iter, check_every=check_every,
                              restart_mode=mode, fixed_K=fixed_K, norm_A=nA, norm_Q=nQ,
-                             warm_fallback=warm_fallback, momentum=momentum)
-    xo, yo, ro, lo = orc.solve(qp, os_, x0=x0, y0=y0, omega0=omega0, log_cap=100000)
+                             warm_fallback=warm_fallback, momentum=momentum,
+                             detect_infeasibility=1 if detect else 0)
+    if precondition:
+        xo, yo, ro, lo = orc.solve_scaled(sc, qp, dv, dr, os_, x0=x0, y0=y0, omega0=omega0,
+                                          log_cap=100000)
+    else:
+        xo, yo, ro, lo = orc.solve(qp, os_, x0=x0, y0=y0, omega0=omega0, log_cap=100000)
     gs = qpa.Settings(eps=eps, max_iter=max_iter, check_every=check_every, restart_mode=mode,
                       fixed_K=fixed_K, norm_A=nA, norm_Q=nQ, warm_fallback=warm_fallback,
                       use_graph=use_graph, log_checks=1 if log else 0,
-                      panels_dual=panels[0], panels_primal=panels[1], momentum=momentum)
+                      panels_dual=panels[0], panels_primal=panels[1], momentum=momentum,
+                      precondition=1 if precondition else 0,
+                      detect_infeasibility=1 if detect else 0)
     with qpa.Solver(qp, gs) as s:
+        if scaling_out is not None:
+            scaling_out.append((s.scaling(), (dv, dr) if precondition else None))
         xg, yg, rg = s.solve(x0=x0, y0=y0, omega0=omega0)
         lg = s.check_log()
     return (xo, yo, ro, lo), (xg, yg, rg, lg)
