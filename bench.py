@@ -350,7 +350,7 @@ def bench_warmstart(log, count):
     log(f"[bench] {ntr} label solves (1e-8) in {t_lab:.1f}s")
     t = time.perf_counter()
     model = ws.train(ws.features(fam, tr), ws.targets(X, Y, omega), fam.base.n, fam.base.m,
-                     hidden=(512, 512), epochs=30, batch=256, lr=1e-3, seed=0,
+                     hidden=(512, 512), epochs=30, batch=256, lr=3e-4, seed=0,
                      log=lambda msg: log(f"[bench] train: {msg}"))
     train_s = time.perf_counter() - t
     log(f"[bench] MLP trained in {train_s:.1f}s, loss {model.history[0]:.4f} -> "

@@ -7,10 +7,11 @@
 // K is never formed: its variable row j is row j of P = [Q | -A'] (Q's row in stored
 // order, then A's column j by increasing row index, exactly how P is assembled) and
 // its constraint row i is row i of A.  Each step computes one statistic per row of K
-// (one thread per row, entries in stored order, so sums are deterministic), turns it
-// into f = 1/sqrt(stat) (1 for an empty row), multiplies d by f and rescales every
-// stored value as k * (f_row * f_col).  The product f_row * f_col is commutative, so
-// the copy of A inside P stays the exact negative of A.
+// (one wavefront per row: lane-strided partial results combined by a fixed butterfly,
+// so sums are deterministic), turns it into f = 1/sqrt(stat) (1 for an empty row),
+// multiplies d by f and rescales every stored value as k * (f_row * f_col).  The
+// product f_row * f_col is commutative, so the copy of A inside P stays the exact
+// negative of A.
 //
 // Batches: rows of all instances are concatenated, columns are local to the
 // instance; a row finds its instance by binary search over the offset arrays.
@@ -51,14 +52,22 @@ __device__ __forceinline__ double stat_add(int kind, double a, double v) {
     return a + v;
 }
 
-__global__ void k_row_stats(ScaleView s, int kind) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int WAVES = 4;  // rows per 256-thread workgroup, one wavefront each
+
+__global__ __launch_bounds__(64 * WAVES) void k_row_stats(ScaleView s, int kind) {
+    const int64_t r = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (r >= s.n + s.m) return;
     const int32_t *rp = r < s.n ? s.p_rowptr : s.a_rowptr;
     const double *val = r < s.n ? s.p_val : s.a_val;
     const int64_t row = r < s.n ? r : r - s.n;
     double a = 0.0;
-    for (int32_t e = rp[row]; e < rp[row + 1]; ++e) a = stat_add(kind, a, val[e]);
+    for (int32_t e = rp[row] + lane; e < rp[row + 1]; e += 64) a = stat_add(kind, a, val[e]);
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_xor(a, off, 64);
+        a = kind == SCALE_MAX ? (o > a ? o : a) : a + o;
+    }
+    if (lane != 0) return;
     if (kind == SCALE_L2) a = sqrt(a);
     s.st[r] = a;
     const double fr = a > 0.0 ? 1.0 / sqrt(a) : 1.0;
@@ -66,8 +75,9 @@ __global__ void k_row_stats(ScaleView s, int kind) {
     s.d[r] = s.d[r] * fr;
 }
 
-__global__ void k_apply_scale(ScaleView s) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(64 * WAVES) void k_apply_scale(ScaleView s) {
+    const int64_t r = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (r >= s.n + s.m) return;
     if (r < s.n) {
         // row r of P: local columns < n_i address variables, the rest constraint rows
@@ -79,7 +89,7 @@ __global__ void k_apply_scale(ScaleView s) {
             nl = s.var_off[q + 1] - vb;
         }
         const double fr = s.f[r];
-        for (int32_t e = s.p_rowptr[r]; e < s.p_rowptr[r + 1]; ++e) {
+        for (int32_t e = s.p_rowptr[r] + lane; e < s.p_rowptr[r + 1]; e += 64) {
             const int64_t c = s.p_col[e];
             const double fc = c < nl ? s.f[vb + c] : s.f[s.n + rb + (c - nl)];
             s.p_val[e] = s.p_val[e] * (fr * fc);
@@ -89,7 +99,7 @@ __global__ void k_apply_scale(ScaleView s) {
         int64_t vb = 0;
         if (s.row_off) vb = s.var_off[find_instance(s.row_off, s.count, i)];
         const double fr = s.f[r];
-        for (int32_t e = s.a_rowptr[i]; e < s.a_rowptr[i + 1]; ++e)
+        for (int32_t e = s.a_rowptr[i] + lane; e < s.a_rowptr[i + 1]; e += 64)
             s.a_val[e] = s.a_val[e] * (fr * s.f[vb + s.a_col[e]]);
     }
 }
@@ -128,9 +138,10 @@ int precondition_device(hipStream_t s, const ScaleInput &in, double *work, doubl
     v.f = work + R;
     v.d = d;
     hipLaunchKernelGGL(k_fill_one, dim3(grid_of(R)), dim3(256), 0, s, d, R);
+    const unsigned rows_grid = (unsigned)((R + WAVES - 1) / WAVES);
     auto step = [&](int kind) {
-        hipLaunchKernelGGL(k_row_stats, dim3(grid_of(R)), dim3(256), 0, s, v, kind);
-        hipLaunchKernelGGL(k_apply_scale, dim3(grid_of(R)), dim3(256), 0, s, v);
+        hipLaunchKernelGGL(k_row_stats, dim3(rows_grid), dim3(64 * WAVES), 0, s, v, kind);
+        hipLaunchKernelGGL(k_apply_scale, dim3(rows_grid), dim3(64 * WAVES), 0, s, v);
     };
     for (int t = 0; t < in.ruiz_iters; ++t) step(SCALE_MAX);
     if (in.l2) step(SCALE_L2);
