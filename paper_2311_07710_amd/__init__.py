@@ -8,6 +8,7 @@ if the library has not been built: there is no CPU fallback.
 """
 from ._binding import (  # noqa: F401
     QP_OK, QP_OPTIMAL, QP_ITERATION_LIMIT, QP_TIME_LIMIT, QP_NUMERICAL_ERROR,
+    QP_PRIMAL_INFEASIBLE, QP_DUAL_INFEASIBLE,
     QP_RESTART_ADAPTIVE, QP_RESTART_FIXED_K, QP_RESTART_HALVING, QP_RESTART_NONE,
     QP_MEM_HOST, QP_MEM_DEVICE, QPError, LIB_PATH, SIGNATURES, load,
 )

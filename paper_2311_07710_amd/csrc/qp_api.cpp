@@ -357,6 +357,7 @@ struct qp_handle {
     DevMem x, xbar, xt, xmd0, xmd1, xrs, y, ybar, yrs, x0buf, y0buf;
     DevMem partials_a, partials_p, state, table;
     DevMem ipart_a, ipart_p;    // infeasibility partials (when detection is on)
+    DevMem kpart_a, kpart_p;    // KKT panel partial sums (2 np m and 4 np n doubles)
     Vecs vecs{};
     int32_t nslotA = 0, nslotP = 0;
     State *h_state = nullptr;  // pinned ring of status records
@@ -749,8 +750,13 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
         return rc;
     h->nslotA = h->partA.view.nblk + h->partA.view.nlr;
     h->nslotP = h->partP.view.nblk + h->partP.view.nlr;
-    if ((rc = h->partials_a.alloc((size_t)(h->nslotA + FOLD_SLOTS) * RA_NV * 8)) ||
-        (rc = h->partials_p.alloc((size_t)(h->nslotP + FOLD_SLOTS) * RP_NV * 8)) ||
+    // slots: one per row block, or one per 256 rows when the KKT runs on the panels
+    const int64_t slA = std::max<int64_t>(h->nslotA, (m + BS - 1) / BS);
+    const int64_t slP = std::max<int64_t>(h->nslotP, (n + BS - 1) / BS);
+    if (h->npA > 1 && (rc = h->kpart_a.alloc((size_t)2 * h->npA * m * 8))) return rc;
+    if (h->npP > 1 && (rc = h->kpart_p.alloc((size_t)4 * h->npP * n * 8))) return rc;
+    if ((rc = h->partials_a.alloc((size_t)(slA + FOLD_SLOTS) * RA_NV * 8)) ||
+        (rc = h->partials_p.alloc((size_t)(slP + FOLD_SLOTS) * RP_NV * 8)) ||
         (rc = h->state.alloc(sizeof(State))) || (rc = h->table.alloc(4096 * sizeof(Step))))
         return rc;
     if (h->set.detect_infeasibility &&
@@ -803,6 +809,26 @@ DevSettings dev_settings(const qp_handle *h) {
 }
 
 // one interval of `len` iterations starting with x_md in buffer md_in
+// KKT products of (x, y) and (x-bar, y-bar) reduced into per-block slots (through the
+// column panels when they exist, so the gathers stay in each XCD's L2); *sa and *sp
+// receive the slot counts for launch_decide.
+void enqueue_kkt(qp_handle *h, hipStream_t s, State *st, int32_t *sa, int32_t *sp) {
+    if (h->npA > 1) {
+        *sa = launch_kkt_rows_panels(s, h->panA.view, h->vecs, h->kpart_a.as<double>(),
+                                     h->partials_a.as<double>(), st, h->n, h->m);
+    } else {
+        launch_kkt_rows(s, h->partA.view, h->A, h->vecs, h->partials_a.as<double>(), st);
+        *sa = h->nslotA;
+    }
+    if (h->npP > 1) {
+        *sp = launch_kkt_cols_panels(s, h->panP.view, h->vecs, h->kpart_p.as<double>(),
+                                     h->partials_p.as<double>(), st, h->n);
+    } else {
+        launch_kkt_cols(s, h->partP.view, h->P, h->vecs, h->partials_p.as<double>(), st, h->n);
+        *sp = h->nslotP;
+    }
+}
+
 void enqueue_interval(qp_handle *h, const DevSettings &ds, int md_in, int len, bool timed) {
     hipStream_t s = h->stream;
     const Step *tab = h->table.as<Step>();
@@ -818,14 +844,14 @@ void enqueue_interval(qp_handle *h, const DevSettings &ds, int md_in, int len, b
         if (timed) (void)hipEventRecord(h->prof_ev[4 * j + 2], s);
         md ^= 1;
     }
-    launch_kkt_rows(s, h->partA.view, h->A, h->vecs, h->partials_a.as<double>(), st);
-    launch_kkt_cols(s, h->partP.view, h->P, h->vecs, h->partials_p.as<double>(), st, h->n);
+    int32_t sa, sp;
+    enqueue_kkt(h, s, st, &sa, &sp);
     if (h->set.detect_infeasibility)  // directions in the warm-start buffers (free here)
         launch_infeas(s, h->partA.view, h->A, h->partP.view, h->P, h->vecs,
                       h->x0buf.as<double>(), h->y0buf.as<double>(), h->ipart_a.as<double>(),
                       h->nslotA, h->ipart_p.as<double>(), h->nslotP, st, h->n, h->m);
-    launch_decide(s, DECIDE_CHECK, h->partials_a.as<double>(), h->nslotA,
-                  h->partials_p.as<double>(), h->nslotP, st, h->table.as<Step>(), ds, len);
+    launch_decide(s, DECIDE_CHECK, h->partials_a.as<double>(), sa, h->partials_p.as<double>(),
+                  sp, st, h->table.as<Step>(), ds, len);
     launch_apply(s, h->vecs, md, st, h->n, h->m);
 }
 
@@ -1074,10 +1100,10 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
     launch_state_reset(s, st, omega, ds.max_iter);
     if (warm && h->set.warm_fallback) {
         launch_init(s, h->vecs, x0, y0, n, m, 1);
-        launch_kkt_rows(s, h->partA.view, h->A, h->vecs, h->partials_a.as<double>(), st);
-        launch_kkt_cols(s, h->partP.view, h->P, h->vecs, h->partials_p.as<double>(), st, n);
-        launch_decide(s, DECIDE_FALLBACK, h->partials_a.as<double>(), h->nslotA,
-                      h->partials_p.as<double>(), h->nslotP, st, h->table.as<Step>(), ds, 0);
+        int32_t sa, sp;
+        enqueue_kkt(h, s, st, &sa, &sp);
+        launch_decide(s, DECIDE_FALLBACK, h->partials_a.as<double>(), sa,
+                      h->partials_p.as<double>(), sp, st, h->table.as<Step>(), ds, 0);
         launch_fallback_apply(s, h->vecs, st, n, m);
     } else {
         launch_init(s, h->vecs, x0, y0, n, m, 0);
@@ -1090,10 +1116,12 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
             HIPCHK(hipMemcpy(st, &one, sizeof(State), hipMemcpyHostToDevice));
         }
     }
-    launch_kkt_rows(s, h->partA.view, h->A, h->vecs, h->partials_a.as<double>(), st);
-    launch_kkt_cols(s, h->partP.view, h->P, h->vecs, h->partials_p.as<double>(), st, n);
-    launch_decide(s, DECIDE_INIT, h->partials_a.as<double>(), h->nslotA,
-                  h->partials_p.as<double>(), h->nslotP, st, h->table.as<Step>(), ds, 0);
+    {
+        int32_t sa, sp;
+        enqueue_kkt(h, s, st, &sa, &sp);
+        launch_decide(s, DECIDE_INIT, h->partials_a.as<double>(), sa,
+                      h->partials_p.as<double>(), sp, st, h->table.as<Step>(), ds, 0);
+    }
     HIPCHK(hipMemcpyAsync(&h->h_state[0], st, sizeof(State), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     State last = h->h_state[0];

@@ -170,6 +170,12 @@ void launch_kkt_rows(hipStream_t s, const Blocks &bk, const Csr &A, const Vecs &
                      double *partials, const State *st);
 void launch_kkt_cols(hipStream_t s, const Blocks &bk, const Csr &P, const Vecs &v,
                      double *partials, const State *st, int64_t n);
+// KKT products through the column panels (kpart: 2 np m / 4 np n doubles); return the
+// number of partial slots written for launch_decide
+int32_t launch_kkt_rows_panels(hipStream_t s, const Panels &pn, const Vecs &v, double *kpart,
+                               double *partials, const State *st, int64_t n, int64_t m);
+int32_t launch_kkt_cols_panels(hipStream_t s, const Panels &pn, const Vecs &v, double *kpart,
+                               double *partials, const State *st, int64_t n);
 void launch_decide(hipStream_t s, int mode, double *partA, int32_t nslotA, double *partP,
                    int32_t nslotP, State *st, Step *table, const DevSettings &ds, int32_t len);
 void launch_apply(hipStream_t s, const Vecs &v, int md_out, const State *st, int64_t n,

@@ -1170,11 +1170,13 @@ void launch_fill(hipStream_t s, double *dst, int64_t n, double value) {
 // ---------------------------------------------------------------------------
 namespace qpk {
 
-// chunk partials of a long row in a panel (same protocol as chunk_finish)
-__device__ bool panel_chunk_finish(const Panels &pn, int bi, int lr, double part, double *tot) {
+// chunk partials (W <= 4 values) of a long row in a panel (same protocol as chunk_finish)
+template <int W>
+__device__ bool panel_chunk_finish_w(const Panels &pn, int bi, int lr, const double *part,
+                                     double *tot) {
     __shared__ int is_last;
     if (threadIdx.x == 0) {
-        pn.lr_partial[(size_t)bi * 4] = part;
+        for (int v = 0; v < W; ++v) pn.lr_partial[(size_t)bi * 4 + v] = part[v];
         __threadfence();
         const int old = atomicAdd(&pn.lr_count[lr], 1);
         is_last = (old == pn.lr_nchunk[lr] - 1);
@@ -1184,14 +1186,18 @@ __device__ bool panel_chunk_finish(const Panels &pn, int bi, int lr, double part
     if (threadIdx.x == 0) {
         __threadfence();
         const int f = pn.lr_first[lr], nc = pn.lr_nchunk[lr];
-        double t = 0.0;
+        for (int v = 0; v < W; ++v) tot[v] = 0.0;
         for (int ch = 0; ch < nc; ++ch)
-            t = t + __hip_atomic_load(&pn.lr_partial[(size_t)(f + ch) * 4], __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-        *tot = t;
+            for (int v = 0; v < W; ++v)
+                tot[v] = tot[v] + __hip_atomic_load(&pn.lr_partial[(size_t)(f + ch) * 4 + v],
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&pn.lr_count[lr], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return threadIdx.x == 0;
+}
+
+__device__ bool panel_chunk_finish(const Panels &pn, int bi, int lr, double part, double *tot) {
+    return panel_chunk_finish_w<1>(pn, bi, lr, &part, tot);
 }
 
 // PHASE only distinguishes the dual and primal instances in profiles.
@@ -1278,6 +1284,197 @@ __global__ __launch_bounds__(256) void k_primal_combine(const double *__restrict
     double s = part[j];
     for (int k = 1; k < np; ++k) s = s + part[(size_t)k * n + j];
     primal_epilogue((int)j, s, a, step->p, step->w, step->theta_next, step->w_next);
+}
+
+// KKT products on the column panels.  KIND 0 (rows of A): sums of A x and A x-bar;
+// KIND 1 (rows of P = [Q | -A']): sums of Q x, -A'y, Q x-bar, -A'y-bar, the column
+// deciding the part.  Panel k's sums of row r go to kpart[(w*np + k)*R + r] for output w;
+// the combine kernels add the panels in order and evaluate the rows' KKT terms.
+template <int KIND>
+__global__ __launch_bounds__(BS) void k_panel_kkt(Panels pn, const double *__restrict__ x,
+                                                  const double *__restrict__ xbar,
+                                                  const double *__restrict__ y,
+                                                  const double *__restrict__ ybar, int32_t n,
+                                                  double *__restrict__ kpart,
+                                                  const State *__restrict__ st) {
+    if (st->done) return;
+    const int bi = pn.map[blockIdx.x];
+    if (bi < 0) return;
+    constexpr int W = KIND == 0 ? 2 : 4;
+    __shared__ double prod0[NNZ_BLK];
+    __shared__ double prod1[NNZ_BLK];
+    __shared__ uint8_t isA[KIND == 0 ? 1 : NNZ_BLK];
+    __shared__ double scratch[BS / 64];
+    const PBlock B = pn.blk[bi];
+    const int t = threadIdx.x;
+    {
+        int cols[EPT];
+        double vals[EPT], g0[EPT], g1[EPT];
+        load_block(pn.col, pn.val, B.e0, B.e1, t, cols, vals);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int cc = cols[i];
+            if (KIND == 0) {
+                g0[i] = x[cc];
+                g1[i] = xbar[cc];
+            } else {
+                const bool ya = cc >= n;
+                g0[i] = *(ya ? y + (cc - n) : x + cc);
+                g1[i] = *(ya ? ybar + (cc - n) : xbar + cc);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            prod0[i * BS + t] = vals[i] * g0[i];
+            prod1[i * BS + t] = vals[i] * g1[i];
+            if (KIND == 1) isA[i * BS + t] = cols[i] >= n;
+        }
+    }
+    __syncthreads();
+    const int32_t *rp = pn.rowptr + (size_t)B.panel * (size_t)(pn.R + 1);
+    const size_t stride = (size_t)pn.np * (size_t)pn.R;
+    double *out = kpart + (size_t)B.panel * (size_t)pn.R;
+    if (B.lr < 0) {
+        const int nrows = B.row1 - B.row0;
+        const int G = nrows >= BS ? 1 : lanes_per_row(nrows);
+        for (int rl0 = 0; rl0 < nrows; rl0 += BS / G) {
+            const int rl = rl0 + t / G, lane = t % G;
+            double sv[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) sv[w] = 0.0;
+            if (rl < nrows) {
+                const int row = B.row0 + rl;
+                const int e1 = rp[row + 1] - B.e0;
+                for (int e = rp[row] - B.e0 + lane; e < e1; e += G) {
+                    if (KIND == 0) {
+                        sv[0] = sv[0] + prod0[e];
+                        sv[1] = sv[1] + prod1[e];
+                    } else if (isA[e]) {
+                        sv[1] = sv[1] + prod0[e];
+                        sv[3] = sv[3] + prod1[e];
+                    } else {
+                        sv[0] = sv[0] + prod0[e];
+                        sv[2] = sv[2] + prod1[e];
+                    }
+                }
+            }
+#pragma unroll
+            for (int w = 0; w < W; ++w) sv[w] = group_sum(sv[w], G);
+            if (rl < nrows && lane == 0)
+                for (int w = 0; w < W; ++w) out[w * stride + B.row0 + rl] = sv[w];
+        }
+    } else {
+        double ps[W];
+        if (KIND == 0) {
+            ps[0] = block_sum_lds(prod0, B.e1 - B.e0, scratch);
+            ps[1] = block_sum_lds(prod1, B.e1 - B.e0, scratch);
+        } else {
+            double q0 = 0.0, a0 = 0.0, q1 = 0.0, a1 = 0.0;
+            for (int e = t; e < B.e1 - B.e0; e += BS) {
+                if (isA[e]) {
+                    a0 = a0 + prod0[e];
+                    a1 = a1 + prod1[e];
+                } else {
+                    q0 = q0 + prod0[e];
+                    q1 = q1 + prod1[e];
+                }
+            }
+            ps[0] = block_sum_value(q0, scratch);
+            ps[1] = block_sum_value(a0, scratch);
+            ps[W > 2 ? 2 : 0] = block_sum_value(q1, scratch);
+            ps[W > 3 ? 3 : 0] = block_sum_value(a1, scratch);
+        }
+        double tot[W];
+        if (panel_chunk_finish_w<W>(pn, bi, B.lr, ps, tot))
+            for (int w = 0; w < W; ++w) out[w * stride + B.row0] = tot[w];
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_kkt_rows_combine(const double *__restrict__ kpart,
+                                                         int32_t np, int64_t m, KktRowArgs a,
+                                                         const State *__restrict__ st) {
+    if (st->done) return;
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    double cv[RA_NV];
+    for (int v = 0; v < RA_NV; ++v) cv[v] = 0.0;
+    if (i < m) {
+        double s0 = kpart[i], s1 = kpart[(size_t)np * m + i];
+        for (int k = 1; k < np; ++k) {
+            s0 = s0 + kpart[(size_t)k * m + i];
+            s1 = s1 + kpart[(size_t)(np + k) * m + i];
+        }
+        kkt_row_contrib((int)i, s0, s1, a, cv);
+    }
+    block_reduce_write<RA_NV, 4>(cv, a.partials + (size_t)blockIdx.x * RA_NV);
+}
+
+__global__ __launch_bounds__(BS) void k_kkt_cols_combine(const double *__restrict__ kpart,
+                                                         int32_t np, int64_t n, KktColArgs a,
+                                                         const State *__restrict__ st) {
+    if (st->done) return;
+    const int64_t j = (int64_t)blockIdx.x * BS + threadIdx.x;
+    double cv[RP_NV];
+    for (int v = 0; v < RP_NV; ++v) cv[v] = 0.0;
+    if (j < n) {
+        const size_t sn = (size_t)np * n;
+        double q[2] = {kpart[j], kpart[2 * sn + j]};
+        double na[2] = {kpart[sn + j], kpart[3 * sn + j]};
+        for (int k = 1; k < np; ++k) {
+            const size_t o = (size_t)k * n + j;
+            q[0] = q[0] + kpart[o];
+            na[0] = na[0] + kpart[sn + o];
+            q[1] = q[1] + kpart[2 * sn + o];
+            na[1] = na[1] + kpart[3 * sn + o];
+        }
+        kkt_col_contrib((int)j, q, na, a, cv);
+    }
+    block_reduce_write<RP_NV, 6>(cv, a.partials + (size_t)blockIdx.x * RP_NV);
+}
+
+int32_t launch_kkt_rows_panels(hipStream_t s, const Panels &pn, const Vecs &v, double *kpart,
+                               double *partials, const State *st, int64_t n, int64_t m) {
+    if (m == 0) return 0;
+    if (pn.grid > 0)
+        hipLaunchKernelGGL(k_panel_kkt<0>, dim3(pn.grid), dim3(BS), 0, s, pn,
+                           (const double *)v.x, (const double *)v.xbar, (const double *)nullptr,
+                           (const double *)nullptr, (int32_t)n, kpart, st);
+    KktRowArgs a;
+    a.x = v.x;
+    a.xbar = v.xbar;
+    a.y = v.y;
+    a.ybar = v.ybar;
+    a.yrs = v.yrs;
+    a.b = v.b;
+    a.rt = v.rt;
+    a.dr = v.dr;
+    a.partials = partials;
+    const int32_t g = (int32_t)((m + BS - 1) / BS);
+    hipLaunchKernelGGL(k_kkt_rows_combine, dim3(g), dim3(BS), 0, s, (const double *)kpart,
+                       pn.np, m, a, st);
+    return g;
+}
+
+int32_t launch_kkt_cols_panels(hipStream_t s, const Panels &pn, const Vecs &v, double *kpart,
+                               double *partials, const State *st, int64_t n) {
+    if (pn.grid > 0)
+        hipLaunchKernelGGL(k_panel_kkt<1>, dim3(pn.grid), dim3(BS), 0, s, pn,
+                           (const double *)v.x, (const double *)v.xbar, (const double *)v.y,
+                           (const double *)v.ybar, (int32_t)n, kpart, st);
+    KktColArgs a;
+    a.x = v.x;
+    a.xbar = v.xbar;
+    a.y = v.y;
+    a.ybar = v.ybar;
+    a.xrs = v.xrs;
+    a.c = v.c;
+    a.l = v.l;
+    a.u = v.u;
+    a.dv = v.dv;
+    a.partials = partials;
+    const int32_t g = (int32_t)((n + BS - 1) / BS);
+    hipLaunchKernelGGL(k_kkt_cols_combine, dim3(g), dim3(BS), 0, s, (const double *)kpart,
+                       pn.np, n, a, st);
+    return g;
 }
 
 void launch_dual_panels(hipStream_t s, const Panels &pn, const Vecs &v, int64_t n,
