@@ -187,3 +187,33 @@ def test_batch_equals_single_solves(qpa):
         assert r["iterations"] == rg[i]["iterations"]
         np.testing.assert_allclose(x, xg[batch.var_off[i]:batch.var_off[i + 1]], rtol=1e-9,
                                    atol=1e-9)
+
+
+def test_batch_full_size_sampled(orc, qpa):
+    """The 4096-instance MPC batch the benchmark times (same launch configuration:
+    autotuned team sizes), checked instance by instance against the oracle on a sample
+    that includes the slowest instance of the set."""
+    batch = qpgen.mpc_batch(seed=4, count=4096)
+    bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6))
+    bs.autotune(sample=128, iters=256)
+    gA, gQ = bs.norms()
+    xg, yg, rg = bs.solve()
+    bs.close()
+    assert all(r["status"] == 0 for r in rg)
+    sample = [0, 428, 1000, 2047, 3071, 4095]
+    ref = []
+    for i in sample:
+        qp = batch.instance(i)
+        s = orc.OracleSettings(eps=1e-6, norm_A=gA[i], norm_Q=gQ[i])
+        x, y, r, _ = orc.solve(qp, s)
+        ref.append((x, y, r, gA[i], gQ[i]))
+    for (xo, yo, ro, _, _), i in zip(ref, sample):
+        v0, v1 = batch.var_off[i], batch.var_off[i + 1]
+        r0, r1 = batch.row_off[i], batch.row_off[i + 1]
+        g = rg[i]
+        print(f"  [{i}] oracle it={ro['iterations']} | gpu it={g['iterations']}", flush=True)
+        assert g["iterations"] == ro["iterations"] and g["status"] == ro["status"]
+        assert abs(g["rel_kkt"] - ro["rel_kkt"]) <= 1e-8
+        zo = np.concatenate([xo, yo])
+        zg = np.concatenate([xg[v0:v1], yg[r0:r1]])
+        assert np.max(np.abs(zg - zo)) <= 1e-8 * (1 + np.max(np.abs(zo)))

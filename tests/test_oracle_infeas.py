@@ -103,3 +103,13 @@ def test_no_false_positives(orc, seed):
     assert a[2]["status"] == b[2]["status"] == orc.OPTIMAL
     assert a[2]["iterations"] == b[2]["iterations"]
     np.testing.assert_array_equal(a[0], b[0])
+
+
+def test_farkas_ratio_needs_the_right_bound(orc):
+    # 0 <= x1 (no upper bound), 0 <= x2 <= 2;  0.1 x1 + x2 >= 3 (GE): y = 1 gives
+    # A'y = (0.1, 1): x2's finite upper bound enters the support (margin 3 - 2 = 1),
+    # x1's missing upper bound makes 0.1 a violation: ratio 0.1
+    qp = qp_refs.make_qp(np.eye(2), np.array([[0.1, 1.0]]), [0.0, 0.0], [3.0],
+                         [0.0, 0.0], [np.inf, 2.0], [1])
+    r = orc.infeas_check(qp, np.zeros(2), np.array([1.0]))
+    assert r["primal_ratio"] == pytest.approx(0.1, rel=1e-15)

@@ -130,3 +130,24 @@ def test_preconditioning_helps_badly_scaled_rows(orc):
     _, _, r_pre, _ = orc.solve_scaled(sc, qp, dv, dr, s)
     assert r_pre["status"] == orc.OPTIMAL
     assert r_pre["iterations"] < r_plain["iterations"]
+
+
+@pytest.mark.parametrize("kind", ["ruiz", "l2", "pc"])
+def test_one_step_on_a_two_variable_k(orc, kind):
+    """K = [[diag(q), a'], [a, 0]] with q = (1e-4, 4), a = (100, -2): one step of each kind
+    worked by hand.  Variable row j of K holds q_j and a_j; the constraint row holds a."""
+    q, a = np.array([1e-4, 4.0]), np.array([100.0, -2.0])
+    qp = qp_refs.make_qp(np.diag(q), a[None, :], np.ones(2), [1.0], np.full(2, -1.0),
+                         np.full(2, 1.0), [0])
+    if kind == "ruiz":
+        stat = np.array([100.0, 4.0, 100.0])
+    elif kind == "l2":
+        stat = np.array([np.hypot(1e-4, 100.0), np.hypot(4.0, 2.0), np.hypot(100.0, 2.0)])
+    else:
+        stat = np.array([100.0001, 6.0, 102.0])
+    f = 1.0 / np.sqrt(stat)
+    sc, dv, dr = orc.precondition(qp, 1 if kind == "ruiz" else 0, kind == "l2", kind == "pc")
+    np.testing.assert_allclose(dv, f[:2], rtol=1e-15)
+    np.testing.assert_allclose(dr, f[2:], rtol=1e-15)
+    np.testing.assert_allclose(sc.q_val, q * f[:2] ** 2, rtol=1e-15)
+    np.testing.assert_allclose(sc.a_val, a * f[:2] * f[2], rtol=1e-15)
