@@ -233,6 +233,8 @@ def main():
         out["batched_mpc"] = bench_batch(log)
     if not args.no_classes:
         out["classes"] = bench_classes(log)
+    if not args.no_classes:
+        out["infeasibility"] = bench_infeasibility(log)
     if not args.no_ablation:
         out["ablation"] = bench_ablation(log)
     if not args.no_warmstart:
@@ -364,6 +366,27 @@ def bench_classes(log):
         log(f"[bench] class {name}: n={qp.n} m={qp.m} nnz={nnz} (gen {gen_s:.1f}s, create "
             f"{create_s:.2f}s): status {r['status']}, {r['iterations']} iterations in {dt:.3f}s "
             f"({r['iterations'] / dt:.0f} it/s), relKKT {r['rel_kkt']:.2e}")
+    return out
+
+
+def bench_infeasibility(log):
+    """Infeasibility certificates on the random-QP class at medium size (n = 1.5e5,
+    m = 7.5e4): a primal-infeasible variant (a contradictory row pair) and an unbounded
+    one (a ray of descent along x_0), preprocessed, detection on."""
+    import qpgen
+    import paper_2311_07710_amd as qpa
+    base = qpgen.large_random_qp(seed=12, n=150_000, m=75_000)
+    out = {}
+    for name, qp in (("primal_infeasible", qpgen.with_contradictory_rows(base, 1)),
+                     ("unbounded", qpgen.with_unbounded_ray(base))):
+        with qpa.Solver(qp, qpa.Settings(eps=1e-6, precondition=1, detect_infeasibility=1,
+                                         max_iter=200000, time_limit_s=60.0)) as s:
+            t = time.perf_counter()
+            _, _, r = s.solve()
+            dt = time.perf_counter() - t
+        out[name] = {"status": r["status"], "iterations": r["iterations"], "seconds": dt}
+        log(f"[bench] {name}: status {r['status']} after {r['iterations']} iterations "
+            f"({dt:.3f}s)")
     return out
 
 

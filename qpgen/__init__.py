@@ -26,4 +26,6 @@ from .instances import (  # noqa: F401
     svm_qp,
     primal_infeasible_qp,
     dual_infeasible_qp,
+    with_contradictory_rows,
+    with_unbounded_ray,
 )

@@ -530,3 +530,48 @@ def dual_infeasible_qp(seed: int = 1, n: int = 100, m: int = 50) -> QPInstance:
     Qc.eliminate_zeros()
     return _make(f"dual_infeasible_s{seed}", Qc, A, c, b, l, u, base.row_type,
                  {"class": "dual_infeasible"})
+
+
+def with_contradictory_rows(qp: QPInstance, seed: int = 0) -> QPInstance:
+    """qp plus the pair a'x >= 1, -a'x >= 0 (a: 64 N(0,1) entries in distinct uniform
+    columns): primal infeasible with the Farkas certificate y = 1 on the pair."""
+    rng = np.random.default_rng([seed, 79])
+    k = min(64, qp.n)
+    cols = np.sort(rng.choice(qp.n, k, replace=False))
+    a = np.zeros(qp.n)
+    a[cols] = rng.standard_normal(k)
+    A = sp.vstack([qp.A(), sp.csr_matrix(a[None, :]), sp.csr_matrix(-a[None, :])]).tocsr()
+    return _make(qp.name + "_contradictory", qp.Q(), A, qp.c, np.concatenate([qp.b, [1.0, 0.0]]),
+                 qp.l, qp.u, np.concatenate([qp.row_type, [GE, GE]]).astype(np.uint8),
+                 {"class": "primal_infeasible"})
+
+
+def with_unbounded_ray(qp: QPInstance) -> QPInstance:
+    """qp made unbounded below along +e_0: Q's row and column 0 zeroed, x_0 without an
+    upper bound, c_0 = -1, column 0 of A zeroed on EQ rows and made >= 0 on GE rows (so
+    A e_0 >= 0).  qp's feasible point (meta "x_feasible") with x_0 moved to its lower
+    bound stays feasible: b is re-derived on EQ rows and lowered where needed on GE rows."""
+    Q = qp.Q().tolil()
+    Q[0, :] = 0.0
+    Q[:, 0] = 0.0
+    A = qp.A().tocsc()
+    col = A[:, 0].toarray().ravel()
+    eq = qp.row_type == EQ
+    col[eq] = 0.0
+    col[~eq] = np.abs(col[~eq])
+    A = A.tolil()
+    A[:, 0] = col[:, None]
+    c = qp.c.copy()
+    c[0] = -1.0
+    u = qp.u.copy()
+    u[0] = np.inf
+    Ac = sp.csr_matrix(A)
+    Ac.eliminate_zeros()
+    Qc = sp.csr_matrix(Q)
+    Qc.eliminate_zeros()
+    xf = np.array(qp.meta["x_feasible"], dtype=np.float64)
+    xf[0] = qp.l[0] if np.isfinite(qp.l[0]) else 0.0
+    ax = Ac @ xf
+    b = np.where(eq, ax, np.minimum(qp.b, ax))
+    return _make(qp.name + "_unbounded", Qc, Ac, c, b, qp.l, u, qp.row_type,
+                 {"class": "dual_infeasible", "x_feasible": xf})

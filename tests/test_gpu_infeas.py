@@ -36,6 +36,18 @@ def test_infeasible_status_matches_oracle(orc, qpa, kind, seed, pre):
 
 
 @pytest.mark.parametrize("panels", [(1, 1), (4, 4)])
+@pytest.mark.parametrize("kind", ["primal", "dual"])
+def test_larger_instances_with_panels(orc, qpa, kind, panels):
+    base = qpgen.large_random_qp(seed=12, n=3000, m=1500)
+    qp = qpgen.with_contradictory_rows(base, 1) if kind == "primal" else qpgen.with_unbounded_ray(base)
+    o, g = _pair(orc, qpa, qp, eps=1e-6, max_iter=50000, detect=True, panels=panels)
+    print(f"  {qp.name}: oracle {o[2]['status']}@{o[2]['iterations']}, "
+          f"gpu {g[2]['status']}@{g[2]['iterations']}", flush=True)
+    assert g[2]["status"] == o[2]["status"] == (4 if kind == "primal" else 5)
+    assert g[2]["iterations"] == o[2]["iterations"]
+
+
+@pytest.mark.parametrize("panels", [(1, 1), (4, 4)])
 def test_detection_on_keeps_feasible_solves(orc, qpa, panels):
     qp = qpgen.large_random_qp(seed=22, n=4000, m=2000)
     o, g = _pair(orc, qpa, qp, eps=1e-6, detect=True, panels=panels)

@@ -113,3 +113,27 @@ def test_farkas_ratio_needs_the_right_bound(orc):
                          [0.0, 0.0], [np.inf, 2.0], [1])
     r = orc.infeas_check(qp, np.zeros(2), np.array([1.0]))
     assert r["primal_ratio"] == pytest.approx(0.1, rel=1e-15)
+
+
+def test_transforms_on_a_larger_instance(orc):
+    base = qpgen.large_random_qp(seed=12, n=3000, m=1500)
+    pi = qpgen.with_contradictory_rows(base, 1)
+    A = pi.A()
+    y = np.zeros(pi.m)
+    y[-2:] = 1.0
+    assert np.abs(A.T @ y).max() == 0.0 and pi.b @ y == 1.0
+    ub = qpgen.with_unbounded_ray(base)
+    Q, A = ub.Q(), ub.A()
+    e0 = np.zeros(ub.n)
+    e0[0] = 1.0
+    assert np.abs(Q @ e0).max() == 0.0 and ub.c @ e0 < 0 and np.isinf(ub.u[0])
+    Ae = A @ e0
+    assert np.all(Ae[ub.row_type == 0] == 0.0) and np.all(Ae[ub.row_type == 1] >= 0.0)
+    xf = ub.meta["x_feasible"]
+    ax = A @ xf
+    eq = ub.row_type == 0
+    assert np.all(ax[eq] == ub.b[eq]) and np.all(ax[~eq] >= ub.b[~eq])
+    assert np.all(xf >= ub.l) and np.all(xf <= ub.u)
+    for qp, want in ((pi, orc.PRIMAL_INFEASIBLE), (ub, orc.DUAL_INFEASIBLE)):
+        r = orc.solve(qp, orc.OracleSettings(eps=1e-6, detect_infeasibility=1, max_iter=50000))[2]
+        assert r["status"] == want
