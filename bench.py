@@ -415,7 +415,12 @@ def bench_warmstart(log, count):
                      hidden=(512, 512), epochs=30, batch=256, lr=3e-4, seed=0,
                      log=lambda msg: log(f"[bench] train: {msg}"))
     train_s = time.perf_counter() - t
-    log(f"[bench] MLP trained in {train_s:.1f}s, loss {model.history[0]:.4f} -> "
+    # GEMM work of training: forward 2*in*out per layer and sample, backward twice that
+    sizes = model.mlp.sizes
+    steps = 30 * (ntr // 256)
+    gemm_flops = 3.0 * 2.0 * sum(a * b for a, b in zip(sizes[:-1], sizes[1:])) * 256 * steps
+    log(f"[bench] MLP trained in {train_s:.1f}s ({gemm_flops / train_s / 1e12:.2f} TFLOP/s of "
+        f"BF16 GEMM work incl. host loop), loss {model.history[0]:.4f} -> "
         f"{model.history[-1]:.4f}")
     t = time.perf_counter()
     x0, y0, w0 = model.predict(ws.features(fam, te))
@@ -435,7 +440,9 @@ def bench_warmstart(log, count):
             "cold_seconds": t_cold, "warm_seconds": t_warm, "inference_seconds": pred_s,
             "warm_kept": kept, "warm_optimal": okw, "held_out": int(te.size),
             "label_solve_seconds": t_lab, "train_seconds": train_s,
-            "loss_first_epoch": model.history[0], "loss_last_epoch": model.history[-1]}
+            "loss_first_epoch": model.history[0], "loss_last_epoch": model.history[-1],
+            "mlp_train_gemm_tflops": gemm_flops / train_s / 1e12,
+            "mlp_bf16_peak_tflops": 2500.0}
 
 
 if __name__ == "__main__":
