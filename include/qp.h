@@ -157,6 +157,9 @@ typedef struct {
                                 descends (c'dx < 0) with ||Q dx||_inf and the row violations
                                 of A dx below eps_infeasible * |c'dx|.  Default 0 */
     double eps_infeasible;   /* certificate tolerance; default 1e-8 */
+    int32_t check_symmetry;  /* 1: qp_create rejects a Q that differs from its transpose
+                                (pattern or value, per instance); PSD is never checked.
+                                Default 0 */
 } qp_settings;
 
 typedef struct {

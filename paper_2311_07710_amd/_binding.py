@@ -50,7 +50,8 @@ class qp_settings(C.Structure):
                 ("use_graph", C.c_int32), ("profile", C.c_int32), ("log_checks", C.c_int32),
                 ("device", C.c_int32), ("panels_dual", C.c_int32), ("panels_primal", C.c_int32),
                 ("momentum", C.c_int32), ("precondition", C.c_int32), ("ruiz_iters", C.c_int32),
-                ("detect_infeasibility", C.c_int32), ("eps_infeasible", C.c_double)]
+                ("detect_infeasibility", C.c_int32), ("eps_infeasible", C.c_double),
+                ("check_symmetry", C.c_int32)]
 
 
 class qp_warm_start(C.Structure):

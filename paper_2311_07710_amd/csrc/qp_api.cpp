@@ -420,6 +420,7 @@ void qp_default_settings(qp_settings *s) {
     s->ruiz_iters = 10;
     s->detect_infeasibility = 0;
     s->eps_infeasible = 1e-8;
+    s->check_symmetry = 0;
 }
 
 const char *qp_last_error(void) { return qph::g_err.c_str(); }
@@ -575,7 +576,7 @@ struct HostProblem {
 };
 
 // Copies the problem to host vectors and validates it (no device work for host input).
-int gather_single(const qp_problem_desc *d, HostProblem &hp) {
+int gather_single(const qp_problem_desc *d, HostProblem &hp, const qp_settings &s) {
     const int64_t n = d->n, m = d->m;
     const int ms = d->mem_space;
     auto &qr = hp.qr, &qc = hp.qc, &ar = hp.ar, &ac = hp.ac;
@@ -631,6 +632,8 @@ int gather_single(const qp_problem_desc *d, HostProblem &hp) {
     const int64_t pnnz = d->Q.nnz + (m > 0 ? d->A.nnz : 0);
     if (pnnz >= ((int64_t)1 << 31) || n + m >= ((int64_t)1 << 31))
         return fail(QP_ERR_INVALID_ARGUMENT, "problem exceeds int32 indexing");
+    if (s.check_symmetry)
+        if ((rc = qph::check_symmetric(n, qr.data(), qc.data(), qv.data(), 0))) return rc;
     return QP_OK;
 }
 
@@ -920,7 +923,9 @@ int qp_create(const qp_problem_desc *d, const qp_settings *settings, qp_handle *
     if (d->num_instances < 1) return fail(QP_ERR_INVALID_ARGUMENT, "num_instances must be >= 1");
     HostProblem hp;
     if (d->num_instances == 1 && d->mem_space == QP_MEM_HOST)
-        if ((rc = gather_single(d, hp))) return rc;  // validation before any device work
+        if ((rc = gather_single(d, hp, s))) return rc;  // validation before any device work
+    if (d->num_instances > 1 && d->mem_space == QP_MEM_HOST)
+        if ((rc = qpb::validate_batch_host(d, &s))) return rc;
     HIPCHK(hipSetDevice(s.device));
     qp_handle *h = new qp_handle();
     h->n = d->n;
@@ -944,7 +949,7 @@ int qp_create(const qp_problem_desc *d, const qp_settings *settings, qp_handle *
     if (d->num_instances > 1) {
         rc = qpb::create_batch(d, &h->set, h->stream, &h->batch);
     } else {
-        if (d->mem_space == QP_MEM_DEVICE) rc = gather_single(d, hp);
+        if (d->mem_space == QP_MEM_DEVICE) rc = gather_single(d, hp, s);
         if (!rc) rc = create_single(d, h, hp);
         if (!rc) rc = estimate_norms(h);
         if (!rc && !(h->norm_A > 0.0) && !(h->norm_Q > 0.0))

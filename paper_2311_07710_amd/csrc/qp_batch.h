@@ -10,6 +10,19 @@ namespace qpb {
 
 struct BatchData;
 
+// host pointers to a batch's arrays (Q and A row pointers over all instances, local
+// column indices)
+struct BatchArrays {
+    const int32_t *qr, *qc;
+    const double *qv;
+    const int32_t *ar, *ac;
+    const uint8_t *rt;
+    const double *l, *u;
+};
+int validate_batch_arrays(const qp_problem_desc *d, const qp_settings *s, const BatchArrays &a);
+// the same checks straight from a host-memory descriptor, before any device work
+int validate_batch_host(const qp_problem_desc *d, const qp_settings *s);
+
 int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t stream,
                  BatchData **out);
 void destroy_batch(BatchData *b);

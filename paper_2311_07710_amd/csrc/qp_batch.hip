@@ -945,6 +945,69 @@ static int upload_vectors(BatchData *bd, const std::vector<double> &c, const std
     return QP_OK;
 }
 
+// Host checks of a batch descriptor's arrays (no device work): offsets, row pointers,
+// row types, bounds, per-instance column ranges, int32 limits, and Q's symmetry when
+// settings.check_symmetry is set.
+int validate_batch_arrays(const qp_problem_desc *d, const qp_settings *s, const BatchArrays &a) {
+    const int32_t B = d->num_instances;
+    const int64_t n = d->n, m = d->m;
+    const int64_t *vo = d->var_off, *ro = d->row_off;
+    if (!vo || !ro) return fail(QP_ERR_INVALID_ARGUMENT, "batch problems need var_off and row_off");
+    if (vo[0] != 0 || ro[0] != 0 || vo[B] != n || ro[B] != m)
+        return fail(QP_ERR_BATCH_MISMATCH, "var_off/row_off do not span [0,n) and [0,m)");
+    for (int i = 0; i < B; ++i)
+        if (vo[i + 1] <= vo[i] || ro[i + 1] < ro[i])
+            return fail(QP_ERR_BATCH_MISMATCH, "every instance needs n_i > 0 and m_i >= 0");
+    if (n + m >= ((int64_t)1 << 31)) return fail(QP_ERR_INVALID_ARGUMENT, "batch exceeds int32");
+    const int64_t pnnz = d->Q.nnz + (m > 0 ? d->A.nnz : 0);
+    if (pnnz >= ((int64_t)1 << 31)) return fail(QP_ERR_INVALID_ARGUMENT, "batch exceeds int32");
+    if (a.qr[0] != 0 || a.qr[n] != d->Q.nnz || (m > 0 && (a.ar[0] != 0 || a.ar[m] != d->A.nnz)))
+        return fail(QP_ERR_INVALID_ARGUMENT, "row pointers do not match nnz");
+    for (int64_t j = 0; j < n; ++j)
+        if (a.qr[j + 1] < a.qr[j]) return fail(QP_ERR_INVALID_ARGUMENT, "Q.row_ptr decreases");
+    for (int64_t i = 0; i < m; ++i) {
+        if (a.ar[i + 1] < a.ar[i]) return fail(QP_ERR_INVALID_ARGUMENT, "A.row_ptr decreases");
+        if (a.rt[i] > 1) return fail(QP_ERR_INVALID_ARGUMENT, "row_type must be 0 or 1");
+    }
+    for (int64_t j = 0; j < n; ++j)
+        if (!(a.l[j] <= a.u[j]) || a.l[j] == INFINITY || a.u[j] == -INFINITY)
+            return fail(QP_ERR_INVALID_ARGUMENT, "invalid bounds at variable %lld", (long long)j);
+    for (int i = 0; i < B; ++i) {
+        const int64_t nv = vo[i + 1] - vo[i];
+        for (int64_t r = ro[i]; r < ro[i + 1]; ++r)
+            for (int64_t e = a.ar[r]; e < a.ar[r + 1]; ++e)
+                if (a.ac[e] < 0 || a.ac[e] >= nv)
+                    return fail(QP_ERR_INVALID_ARGUMENT, "A column index outside its instance");
+        for (int64_t j = vo[i]; j < vo[i + 1]; ++j)
+            for (int64_t e = a.qr[j]; e < a.qr[j + 1]; ++e)
+                if (a.qc[e] < 0 || a.qc[e] >= nv)
+                    return fail(QP_ERR_INVALID_ARGUMENT, "Q column index outside its instance");
+    }
+    if (s->check_symmetry)
+        for (int i = 0; i < B; ++i) {
+            int rc = qph::check_symmetric(vo[i + 1] - vo[i], a.qr + vo[i], a.qc, a.qv, i);
+            if (rc) return rc;
+        }
+    return QP_OK;
+}
+
+int validate_batch_host(const qp_problem_desc *d, const qp_settings *s) {
+    const int64_t m = d->m;
+    static const int32_t zero = 0;
+    std::vector<uint8_t> rt;
+    std::vector<double> l, u;
+    if (!d->row_type) rt.assign((size_t)m, 0);
+    if (!d->l) l.assign((size_t)d->n, -INFINITY);
+    if (!d->u) u.assign((size_t)d->n, INFINITY);
+    if (m > 0 && (!d->A.row_ptr || !d->b || (d->A.nnz > 0 && (!d->A.col_idx || !d->A.val))))
+        return fail(QP_ERR_INVALID_ARGUMENT, "A arrays and b are required when m > 0");
+    if (!d->c) return fail(QP_ERR_INVALID_ARGUMENT, "c is required");
+    BatchArrays arr{d->Q.row_ptr, d->Q.col_idx, d->Q.val, m > 0 ? d->A.row_ptr : &zero,
+                    d->A.col_idx, d->row_type ? d->row_type : rt.data(),
+                    d->l ? d->l : l.data(), d->u ? d->u : u.data()};
+    return validate_batch_arrays(d, s, arr);
+}
+
 int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t stream,
                  BatchData **out) {
     *out = nullptr;
@@ -957,18 +1020,7 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
     bd->stream = stream;
     bd->var_off.assign(d->var_off, d->var_off + B + 1);
     bd->row_off.assign(d->row_off, d->row_off + B + 1);
-    auto bad = [&](int code, const char *msg) {
-        delete bd;
-        return fail(code, "%s", msg);
-    };
-    if (bd->var_off[0] != 0 || bd->row_off[0] != 0 || bd->var_off[B] != d->n ||
-        bd->row_off[B] != d->m)
-        return bad(QP_ERR_BATCH_MISMATCH, "var_off/row_off do not span [0,n) and [0,m)");
-    for (int i = 0; i < B; ++i)
-        if (bd->var_off[i + 1] <= bd->var_off[i] || bd->row_off[i + 1] < bd->row_off[i])
-            return bad(QP_ERR_BATCH_MISMATCH, "every instance needs n_i > 0 and m_i >= 0");
     const int64_t n = d->n, m = d->m;
-    if (n + m >= ((int64_t)1 << 31)) return bad(QP_ERR_INVALID_ARGUMENT, "batch exceeds int32");
     bd->ntot = n;
     bd->mtot = m;
     std::vector<int32_t> qr, qc, ar, ac;
@@ -1008,37 +1060,23 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
     } else {
         u.assign(n, INFINITY);
     }
-    // validation
-    if (qr[0] != 0 || qr[n] != d->Q.nnz || ar[0] != 0 || (m > 0 && ar[m] != d->A.nnz))
-        return bad(QP_ERR_INVALID_ARGUMENT, "row pointers do not match nnz");
-    for (int64_t j = 0; j < n; ++j)
-        if (qr[j + 1] < qr[j]) return bad(QP_ERR_INVALID_ARGUMENT, "Q.row_ptr decreases");
-    for (int64_t i = 0; i < m; ++i) {
-        if (ar[i + 1] < ar[i]) return bad(QP_ERR_INVALID_ARGUMENT, "A.row_ptr decreases");
-        if (rt[i] > 1) return bad(QP_ERR_INVALID_ARGUMENT, "row_type must be 0 or 1");
+    {
+        BatchArrays arr{qr.data(), qc.data(), qv.data(), ar.data(), ac.data(), rt.data(),
+                        l.data(), u.data()};
+        if ((rc = validate_batch_arrays(d, s, arr))) {
+            delete bd;
+            return rc;
+        }
     }
-    for (int64_t j = 0; j < n; ++j)
-        if (!(l[j] <= u[j]) || l[j] == INFINITY || u[j] == -INFINITY)
-            return bad(QP_ERR_INVALID_ARGUMENT, "invalid bounds");
     const int64_t pnnz = d->Q.nnz + (m > 0 ? d->A.nnz : 0);
-    if (pnnz >= ((int64_t)1 << 31)) return bad(QP_ERR_INVALID_ARGUMENT, "batch exceeds int32");
     std::vector<int32_t> pr(n + 1, 0), pc((size_t)pnnz);
     std::vector<double> pv((size_t)pnnz);
     {
+        // (indices were validated above)
         std::vector<int64_t> acount(n, 0);
-        for (int i = 0; i < B; ++i) {
-            const int64_t nv = bd->var_off[i + 1] - bd->var_off[i];
+        for (int i = 0; i < B; ++i)
             for (int64_t r = bd->row_off[i]; r < bd->row_off[i + 1]; ++r)
-                for (int64_t e = ar[r]; e < ar[r + 1]; ++e) {
-                    if (ac[e] < 0 || ac[e] >= nv)
-                        return bad(QP_ERR_INVALID_ARGUMENT, "A column index outside its instance");
-                    acount[bd->var_off[i] + ac[e]]++;
-                }
-            for (int64_t j = bd->var_off[i]; j < bd->var_off[i + 1]; ++j)
-                for (int64_t e = qr[j]; e < qr[j + 1]; ++e)
-                    if (qc[e] < 0 || qc[e] >= nv)
-                        return bad(QP_ERR_INVALID_ARGUMENT, "Q column index outside its instance");
-        }
+                for (int64_t e = ar[r]; e < ar[r + 1]; ++e) acount[bd->var_off[i] + ac[e]]++;
         for (int64_t j = 0; j < n; ++j) pr[j + 1] = (int32_t)(pr[j] + (qr[j + 1] - qr[j]) + acount[j]);
         std::vector<int64_t> next(n);
         for (int64_t j = 0; j < n; ++j) {

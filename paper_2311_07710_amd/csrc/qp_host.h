@@ -4,7 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
+#include <tuple>
+#include <vector>
 
 #include "../../include/qp.h"
 
@@ -72,5 +75,41 @@ struct DevMem {
     }
     template <class T> T *as() const { return (T *)p; }
 };
+
+// Q (n x n, rows rowptr[0..n], which may be offsets into a larger array) must equal its
+// transpose exactly, entry by entry (duplicates are summed on both sides).
+inline int check_symmetric(int64_t n, const int32_t *rowptr, const int32_t *col,
+                           const double *val, int instance) {
+    std::vector<std::tuple<int32_t, int32_t, double>> e, t;
+    const int64_t base = rowptr[0];
+    e.reserve((size_t)(rowptr[n] - base));
+    for (int64_t r = 0; r < n; ++r)
+        for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+            e.emplace_back((int32_t)r, col[k], val[k]);
+            t.emplace_back(col[k], (int32_t)r, val[k]);
+        }
+    auto canon = [](std::vector<std::tuple<int32_t, int32_t, double>> &v) {
+        std::sort(v.begin(), v.end());
+        std::vector<std::tuple<int32_t, int32_t, double>> out;
+        for (auto &x : v) {
+            if (!out.empty() && std::get<0>(out.back()) == std::get<0>(x) &&
+                std::get<1>(out.back()) == std::get<1>(x))
+                std::get<2>(out.back()) += std::get<2>(x);
+            else
+                out.push_back(x);
+        }
+        v.swap(out);
+    };
+    canon(e);
+    canon(t);
+    if (e.size() != t.size())
+        return fail(QP_ERR_INVALID_ARGUMENT, "Q of instance %d is not symmetric (pattern)", instance);
+    for (size_t k = 0; k < e.size(); ++k)
+        if (std::get<0>(e[k]) != std::get<0>(t[k]) || std::get<1>(e[k]) != std::get<1>(t[k]) ||
+            std::get<2>(e[k]) != std::get<2>(t[k]))
+            return fail(QP_ERR_INVALID_ARGUMENT, "Q of instance %d is not symmetric at (%d, %d)",
+                        instance, (int)std::get<0>(e[k]), (int)std::get<1>(e[k]));
+    return QP_OK;
+}
 
 }  // namespace qph

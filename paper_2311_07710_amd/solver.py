@@ -45,6 +45,7 @@ class Settings:
     ruiz_iters: int = 10
     detect_infeasibility: int = 0
     eps_infeasible: float = 1e-8
+    check_symmetry: int = 0
 
     def c_struct(self) -> B.qp_settings:
         s = B.qp_settings()

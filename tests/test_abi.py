@@ -130,3 +130,57 @@ def test_null_arguments():
     r = B.qp_result()
     assert lib.qp_solve(None, None, C.byref(r), None, None) == B.QP_ERR_INVALID_ARGUMENT
     assert "null" in lib.qp_last_error().decode()
+
+
+def _batch_create_rc(batch, **settings):
+    lib = qpa.load()
+    keep = _Keep(False)
+    d = _desc(batch, keep, batch=True)
+    h = C.c_void_p()
+    rc = lib.qp_create(C.byref(d), C.byref(Settings(**settings).c_struct()), C.byref(h))
+    if rc == 0:
+        lib.qp_free(h)
+    return rc, lib.qp_last_error().decode()
+
+
+def _small_batch():
+    import dataclasses
+    insts = [qpgen.tiny_random_qp(s, n=12, m=6, n_eq=3) for s in (1, 2, 3)]
+    b = qpgen.concat_batch(insts)
+    return dataclasses.replace(b, var_off=b.var_off.copy(), row_off=b.row_off.copy(),
+                               a_col=b.a_col.copy(), q_col=b.q_col.copy(), l=b.l.copy(),
+                               row_type=b.row_type.copy(), q_val=b.q_val.copy())
+
+
+@pytest.mark.parametrize("mutate,code,needle", [
+    (lambda b: b.var_off.__setitem__(1, b.var_off[2]), 4, "n_i > 0"),
+    (lambda b: b.var_off.__setitem__(0, 1), 4, "do not span"),
+    (lambda b: b.row_off.__setitem__(1, b.row_off[2] + 1), 4, "m_i >= 0"),
+    (lambda b: b.a_col.__setitem__(0, 12), 1, "A column index outside its instance"),
+    (lambda b: b.q_col.__setitem__(5, -1), 1, "Q column index outside its instance"),
+    (lambda b: b.row_type.__setitem__(4, 3), 1, "row_type"),
+    (lambda b: b.l.__setitem__(7, np.inf), 1, "invalid bounds at variable 7"),
+])
+def test_malformed_batch_rejected_on_host(mutate, code, needle):
+    b = _small_batch()
+    mutate(b)
+    rc, msg = _batch_create_rc(b)
+    assert rc == code and needle in msg, (rc, msg)
+
+
+def test_asymmetric_q_rejected_when_checked():
+    qp = _tiny()
+    qp.q_val = qp.q_val.copy()
+    # perturb one strictly off-diagonal entry only
+    rows = np.repeat(np.arange(qp.n), np.diff(qp.q_rowptr))
+    k = int(np.flatnonzero(rows != qp.q_col)[0])
+    qp.q_val[k] += 1e-9
+    rc, msg = _create_rc(qp, check_symmetry=1)
+    assert rc == B.QP_ERR_INVALID_ARGUMENT and "not symmetric at" in msg
+    b = _small_batch()
+    rows = np.repeat(np.arange(int(b.var_off[-1])), np.diff(b.q_rowptr))
+    loc = rows - np.repeat(b.var_off[:-1], np.diff(b.var_off))[rows]
+    k = int(np.flatnonzero(loc != b.q_col)[-1])
+    b.q_val[k] += 1.0
+    rc, msg = _batch_create_rc(b, check_symmetry=1)
+    assert rc == B.QP_ERR_INVALID_ARGUMENT and "instance 2 is not symmetric" in msg

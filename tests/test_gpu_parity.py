@@ -374,3 +374,17 @@ def test_portfolio_full_size(orc, qpa):
     nQ, _ = orc.norm_Q(qp, 40, 1e-7)
     o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=64, norms=(nA, nQ))
     _assert_parity(orc, qp, o, g)
+
+
+def test_symmetry_check_accepts_generated_instances(orc, qpa):
+    qp = qpgen.tiny_random_qp(1)
+    o, g = _pair(orc, qpa, qp, eps=1e-6)
+    with qpa.Solver(qp, qpa.Settings(eps=1e-6, norm_A=o[2]["norm_A"], norm_Q=o[2]["norm_Q"],
+                                     check_symmetry=1)) as s:
+        x, y, r = s.solve()
+    assert r["iterations"] == g[2]["iterations"]
+    np.testing.assert_array_equal(x, g[0])
+    batch = qpgen.concat_batch([qpgen.tiny_random_qp(k) for k in (1, 2)])
+    with qpa.BatchSolver(batch, qpa.Settings(eps=1e-6, check_symmetry=1)) as bs:
+        _, _, rb = bs.solve()
+    assert all(r["status"] == 0 for r in rb)
