@@ -84,8 +84,8 @@ def main():
                          "for rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
-              "multi-GPU path; the sharding design is described in DESIGN.md.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no "
+              "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
