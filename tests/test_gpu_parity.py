@@ -388,3 +388,47 @@ def test_symmetry_check_accepts_generated_instances(orc, qpa):
     with qpa.BatchSolver(batch, qpa.Settings(eps=1e-6, check_symmetry=1)) as bs:
         _, _, rb = bs.solve()
     assert all(r["status"] == 0 for r in rb)
+
+
+def _lp_instance(seed=31, n=60, m=30):
+    """A bounded LP (Q = 0, no stored entries): min c'x, Ax >= b, 0 <= x <= 10."""
+    rng = np.random.default_rng(seed)
+    A = np.where(rng.random((m, n)) < 0.2, rng.standard_normal((m, n)), 0.0)
+    xf = rng.uniform(0.5, 2.0, n)
+    b = A @ xf - rng.uniform(0.0, 1.0, m)
+    qp = qp_refs.make_qp(np.zeros((n, n)), A, rng.standard_normal(n), b, np.zeros(n),
+                         np.full(n, 10.0), np.ones(m, dtype=int))
+    assert qp.q_nnz == 0
+    return qp
+
+
+def test_linear_program_without_q(orc, qpa):
+    qp = _lp_instance()
+    o, g = _pair(orc, qpa, qp, eps=1e-6)
+    _assert_parity(orc, qp, o, g)
+    assert g[2]["status"] == 0 and g[2]["norm_Q"] == 0.0
+
+
+def test_single_variable(orc, qpa):
+    # n = 1, m = 1: min 1/2 x^2 - 3x  s.t.  x >= 1, x <= 2  ->  x = 2
+    qp = qp_refs.make_qp(np.eye(1), np.ones((1, 1)), [-3.0], [1.0], [-np.inf], [2.0], [1])
+    o, g = _pair(orc, qpa, qp, eps=1e-9)
+    _assert_parity(orc, qp, o, g)
+    assert g[0][0] == pytest.approx(2.0, abs=1e-6)
+
+
+def test_rows_without_entries(orc, qpa):
+    """Constraint rows with no nonzeros (0 >= b_i with b_i <= 0, and 0 = 0): empty row
+    blocks read the arrays' pad entry and contribute nothing."""
+    qp0 = qpgen.tiny_random_qp(5)
+    A = qp0.A().toarray()
+    A[::3, :] = 0.0                       # every third row empty
+    b = qp0.b.copy()
+    empty = ~A.any(axis=1)
+    b[empty & (qp0.row_type == 1)] = -1.0
+    b[empty & (qp0.row_type == 0)] = 0.0
+    Q, _ = qp0.dense()
+    qp = qp_refs.make_qp(Q, A, qp0.c, b, qp0.l, qp0.u, qp0.row_type)
+    assert (np.diff(qp.a_rowptr) == 0).sum() >= 10
+    o, g = _pair(orc, qpa, qp, eps=1e-6)
+    _assert_parity(orc, qp, o, g)
