@@ -14,7 +14,7 @@
 // P = [Q | -A'] (n rows, columns >= n address y), so the primal phase is a
 // single streaming pass gathering from (x_md, y).  Rows are grouped on the
 // host into blocks of <= NNZ_BLK nonzeros and <= BS rows; a workgroup streams
-// its nonzeros with coalesced non-temporal loads, gathers the vector entries
+// its nonzeros with coalesced loads, gathers the vector entries
 // and stages the products in LDS, then each row is summed in CSR order
 // (several lanes per row only when a block holds few rows).  HBM-bound: no
 // MFMA anywhere on this path.
@@ -139,6 +139,15 @@ __device__ __forceinline__ void dual_epilogue(int i, double v, double *__restric
 // in flight together.  Lanes past the block's end read entry e0 (device arrays carry a
 // zero pad entry, so e0 is readable even for an empty block at the end of an array) and
 // get value 0: their products are zero and never summed.
+//
+// Cache policy (measured on the large random QP): P = [Q | -A'] is streamed with
+// non-temporal loads so it does not evict the gathered vectors; A (a third of P's size)
+// is streamed with ordinary loads, which lets it stay resident in the 256 MB MALL
+// from one iteration to the next (dual phase 46.6 -> 42.1 us).  Ordinary loads for P
+// as well were 7 % slower: the per-iteration working set then exceeds the MALL.
+enum Stream { STREAM_A = 0, STREAM_P = 1 };
+
+template <int SRC>
 __device__ __forceinline__ void load_block(const int32_t *__restrict__ col,
                                            const double *__restrict__ val, int e0, int e1,
                                            int t, int (&cols)[EPT], double (&vals)[EPT]) {
@@ -146,8 +155,14 @@ __device__ __forceinline__ void load_block(const int32_t *__restrict__ col,
     for (int i = 0; i < EPT; ++i) {
         const int e = e0 + i * BS + t;
         const int ee = e < e1 ? e : e0;
-        cols[i] = __builtin_nontemporal_load(&col[ee]);
-        const double v = __builtin_nontemporal_load(&val[ee]);
+        double v;
+        if (SRC == STREAM_P) {
+            cols[i] = __builtin_nontemporal_load(&col[ee]);
+            v = __builtin_nontemporal_load(&val[ee]);
+        } else {
+            cols[i] = col[ee];
+            v = val[ee];
+        }
         vals[i] = e < e1 ? v : 0.0;
     }
 }
@@ -166,7 +181,7 @@ __global__ __launch_bounds__(BS) void k_dual(Blocks bk, Csr A, const double *__r
     const int t = threadIdx.x;
     int cols[EPT];
     double vals[EPT];
-    load_block(A.col, A.val, B.e0, B.e1, t, cols, vals);
+    load_block<STREAM_A>(A.col, A.val, B.e0, B.e1, t, cols, vals);
     double g[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) g[i] = xt[cols[i]];
@@ -230,7 +245,7 @@ __global__ __launch_bounds__(BS) void k_primal(Blocks bk, Csr P, PrimalArgs a,
     const int t = threadIdx.x;
     int cols[EPT];
     double vals[EPT];
-    load_block(P.col, P.val, B.e0, B.e1, t, cols, vals);
+    load_block<STREAM_P>(P.col, P.val, B.e0, B.e1, t, cols, vals);
     double g[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -327,7 +342,7 @@ __global__ __launch_bounds__(BS) void k_kkt_rows(Blocks bk, Csr A, KktRowArgs a,
     {
         int cols[EPT];
         double vals[EPT], g0[EPT], g1[EPT];
-        load_block(A.col, A.val, B.e0, B.e1, t, cols, vals);
+        load_block<STREAM_A>(A.col, A.val, B.e0, B.e1, t, cols, vals);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             g0[i] = a.x[cols[i]];
@@ -425,7 +440,7 @@ __global__ __launch_bounds__(BS) void k_kkt_cols(Blocks bk, Csr P, KktColArgs a,
     {
         int cols[EPT];
         double vals[EPT], g0[EPT], g1[EPT];
-        load_block(P.col, P.val, B.e0, B.e1, t, cols, vals);
+        load_block<STREAM_P>(P.col, P.val, B.e0, B.e1, t, cols, vals);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int cc = cols[i];
@@ -640,7 +655,7 @@ __global__ __launch_bounds__(BS) void k_infeas_rows(Blocks bk, Csr A, InfRowArgs
     {
         int cols[EPT];
         double vals[EPT], g[EPT];
-        load_block(A.col, A.val, B.e0, B.e1, t, cols, vals);
+        load_block<STREAM_A>(A.col, A.val, B.e0, B.e1, t, cols, vals);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) g[i] = a.dxh[cols[i]];
 #pragma unroll
@@ -712,7 +727,7 @@ __global__ __launch_bounds__(BS) void k_infeas_cols(Blocks bk, Csr P, InfColArgs
     {
         int cols[EPT];
         double vals[EPT], g[EPT];
-        load_block(P.col, P.val, B.e0, B.e1, t, cols, vals);
+        load_block<STREAM_P>(P.col, P.val, B.e0, B.e1, t, cols, vals);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int cc = cols[i];
@@ -906,7 +921,7 @@ __global__ __launch_bounds__(BS) void k_spmv_plain(Blocks bk, Csr M, const doubl
     {
         int cols[EPT];
         double vals[EPT], g[EPT];
-        load_block(M.col, M.val, B.e0, B.e1, t, cols, vals);
+        load_block<STREAM_P>(M.col, M.val, B.e0, B.e1, t, cols, vals);
         // a missing operand contributes zero; its entries read a valid dummy address
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
@@ -1200,8 +1215,8 @@ __device__ bool panel_chunk_finish(const Panels &pn, int bi, int lr, double part
     return panel_chunk_finish_w<1>(pn, bi, lr, &part, tot);
 }
 
-// PHASE only distinguishes the dual and primal instances in profiles.
-// Gathers v1[c] for c < split and v2[c - split] otherwise.
+// PHASE 0: rows of A (dual phase, ordinary loads); PHASE 1: rows of P (primal phase,
+// non-temporal loads).  Gathers v1[c] for c < split and v2[c - split] otherwise.
 template <int PHASE>
 __global__ __launch_bounds__(BS) void k_panel_spmv(Panels pn, const double *__restrict__ v1,
                                                    const double *__restrict__ v2, int32_t split,
@@ -1215,7 +1230,7 @@ __global__ __launch_bounds__(BS) void k_panel_spmv(Panels pn, const double *__re
     const int t = threadIdx.x;
     int cols[EPT];
     double vals[EPT];
-    load_block(pn.col, pn.val, B.e0, B.e1, t, cols, vals);
+    load_block<PHASE == 0 ? STREAM_A : STREAM_P>(pn.col, pn.val, B.e0, B.e1, t, cols, vals);
     double g[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -1310,7 +1325,7 @@ __global__ __launch_bounds__(BS) void k_panel_kkt(Panels pn, const double *__res
     {
         int cols[EPT];
         double vals[EPT], g0[EPT], g1[EPT];
-        load_block(pn.col, pn.val, B.e0, B.e1, t, cols, vals);
+        load_block<KIND == 0 ? STREAM_A : STREAM_P>(pn.col, pn.val, B.e0, B.e1, t, cols, vals);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int cc = cols[i];

@@ -300,10 +300,11 @@ def test_unconstrained_m0(orc, qpa):
 
 
 def test_row_lengths_around_block_size(orc, qpa):
-    """Rows with 0, 1, 2047, 2048, 2049, 4097 and 6000 nonzeros plus short rows."""
+    """Rows of 0 and 1 nonzeros, either side of 1024 and of the 2048-entry block size,
+    4097 and 6000, among short rows."""
     rng = np.random.default_rng(12)
     n = 7000
-    lens = [0, 1, 2047, 2048, 2049, 5, 4097, 0, 6000, 3] + [7] * 300
+    lens = [0, 1, 1023, 1024, 1025, 2047, 2048, 2049, 5, 4097, 0, 6000, 3] + [7] * 300
     rows, cols, vals = [], [], []
     for i, L in enumerate(lens):
         c = rng.choice(n, size=L, replace=False)
