@@ -400,21 +400,17 @@ __device__ __forceinline__ double proj_box_b(double v, double lo, double hi) {
     return v;
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
-    extern __shared__ double smem[];  // x~ | x_md[0] | x_md[1] | y when they fit
-    __shared__ int s_q;
-    __shared__ State S;
-    __shared__ Step stp[2];
-    __shared__ double red[32 * (NT / 64)];
-    __shared__ double s_last;
+// One instance, start to finish, by the whole team.  LDS says whether the gathered
+// vectors (x~, the x_md ping-pong pair, y) live in LDS.  As a compile-time flag it lets
+// every access to them compile to LDS instructions; chosen at run time through one
+// pointer, they became generic (flat) accesses, which pay vector-memory latency even
+// when the address is in LDS.
+template <int NT, bool LDS>
+__device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSettings &base,
+                                               int id, double *smem, State &S, Step *stp,
+                                               double *red, double &s_last) {
     const int t = threadIdx.x;
-    for (;;) {
-        if (t == 0) s_q = atomicAdd(a.head, 1);
-        __syncthreads();
-        const int q = s_q;
-        if (q >= a.order_count) break;
-        const int id = a.order[q];
+    {
         const int v0 = a.var_off[id], n = a.var_off[id + 1] - v0;
         const int r0 = a.row_off[id], m = a.row_off[id + 1] - r0;
         const int32_t *arp = a.a_rowptr + r0;
@@ -425,10 +421,11 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
         double *ybar = a.ybar + r0, *yrs = a.yrs + r0;
         // the gathered vectors (x~ in the dual phase, x_md and y in the primal
         // phase) live in LDS when the instance fits, else in HBM
-        const bool in_lds = 3 * n + m <= a.lds_doubles;
-        double *xt = in_lds ? smem : a.xt + v0;
-        double *xmd[2] = {in_lds ? smem + n : a.xmd0 + v0, in_lds ? smem + 2 * n : a.xmd1 + v0};
-        double *y = in_lds ? smem + 3 * n : a.y + r0;
+        double *xt = LDS ? smem : a.xt + v0;
+        // (named pointers, not an array indexed at run time, so LDS stays visible)
+        double *const xmd0 = LDS ? smem + n : a.xmd0 + v0;
+        double *const xmd1 = LDS ? smem + 2 * n : a.xmd1 + v0;
+        double *y = LDS ? smem + 3 * n : a.y + r0;
         const double *dvi = a.dscale ? a.dscale + v0 : nullptr;
         const double *dri = a.dscale ? a.dscale + a.ntot + r0 : nullptr;
         const int32_t *lra = a.lrA + a.lrA_off[id];
@@ -450,7 +447,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
             x[j] = xw;
             xbar[j] = pair ? xc : xw;
             xt[j] = xw;
-            xmd[0][j] = xw;
+            xmd0[j] = xw;
             xrs[j] = xw;
         }
         for (int i = t; i < m; i += NT) {
@@ -484,7 +481,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
             const int take = S.used_warm;
             for (int j = t; j < n; j += NT) {
                 const double xv = take ? x[j] : xbar[j];
-                x[j] = xbar[j] = xt[j] = xmd[0][j] = xrs[j] = xv;
+                x[j] = xbar[j] = xt[j] = xmd0[j] = xrs[j] = xv;
             }
             for (int i = t; i < m; i += NT) {
                 const double yv = take ? y[i] : ybar[i];
@@ -533,8 +530,8 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
                 }
                 __syncthreads();
                 // primal phase over P = [Q | -A'] gathering (x_md, y+)
-                const double *xin = xmd[md];
-                double *xout = xmd[md ^ 1];
+                const double *xin = md ? xmd1 : xmd0;
+                double *xout = md ? xmd0 : xmd1;
                 for (int jj = t; jj < n; jj += NT) {
                     if (prp[jj + 1] - prp[jj] > LONG_ROW) continue;
                     const double s = row_dot(a.p_col, a.p_val, prp[jj], prp[jj + 1], [&](int cc) {
@@ -586,7 +583,8 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
                 const int avg = S.cand;
                 for (int j = t; j < n; j += NT) {
                     const double xc = avg ? xbar[j] : x[j];
-                    x[j] = xbar[j] = xt[j] = xmd[md][j] = xrs[j] = xc;
+                    double *xm = md ? xmd1 : xmd0;
+                    x[j] = xbar[j] = xt[j] = xm[j] = xrs[j] = xc;
                 }
                 for (int i = t; i < m; i += NT) {
                     const double yc = avg ? ybar[i] : y[i];
@@ -600,6 +598,28 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
         for (int j = t; j < n; j += NT) a.x_out[v0 + j] = avg ? xbar[j] : x[j];
         for (int i = t; i < m; i += NT) a.y_out[r0 + i] = avg ? ybar[i] : y[i];
         if (t == 0) a.res[id] = S;
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
+    extern __shared__ double smem[];  // x~ | x_md[0] | x_md[1] | y when they fit
+    __shared__ int s_q;
+    __shared__ State S;
+    __shared__ Step stp[2];
+    __shared__ double red[32 * (NT / 64)];
+    __shared__ double s_last;
+    for (;;) {
+        if (threadIdx.x == 0) s_q = atomicAdd(a.head, 1);
+        __syncthreads();
+        const int q = s_q;
+        if (q >= a.order_count) break;
+        const int id = a.order[q];
+        const int n = a.var_off[id + 1] - a.var_off[id], m = a.row_off[id + 1] - a.row_off[id];
+        if (3 * n + m <= a.lds_doubles)
+            solve_instance<NT, true>(a, base, id, smem, S, stp, red, s_last);
+        else
+            solve_instance<NT, false>(a, base, id, smem, S, stp, red, s_last);
         __syncthreads();
     }
 }
