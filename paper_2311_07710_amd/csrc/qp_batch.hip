@@ -38,7 +38,8 @@ using namespace qpk;
 
 constexpr int NCLASS = 4;
 static const int32_t CLASS_LIMIT[NCLASS] = {256, 1024, 2048, 1 << 30};  // n_i + m_i upper bound
-static const int32_t THREAD_CHOICES[4] = {64, 128, 256, 512};
+static const int32_t THREAD_CHOICES[] = {64, 128, 256, 512, 1024};
+constexpr int NCHOICE = (int)(sizeof(THREAD_CHOICES) / sizeof(THREAD_CHOICES[0]));
 
 struct BatchDev {
     int32_t count;
@@ -67,9 +68,15 @@ struct BatchDev {
     const int32_t *lrP_off, *lrP;  // same for rows of P
     const double *dscale;          // preconditioning: D2 of all variables, then D1; or nullptr
     int64_t ntot;                  // variables of all instances
+    // sliced copies of A and P for the iteration's row loops (see build_sliced)
+    const int32_t *sa_inst, *sa_start, *sa_width, *sa_col;
+    const double *sa_val;
+    const int32_t *sp_inst, *sp_start, *sp_width, *sp_col;
+    const double *sp_val;
 };
 
 constexpr int LONG_ROW = 128;
+constexpr int SLICE = 64;  // rows per slice of the sliced layout: one per lane of a wavefront
 
 // ---------------------------------------------------------------------------
 // device helpers
@@ -198,6 +205,29 @@ __device__ __forceinline__ double row_dot(const int32_t *__restrict__ col,
         s = s + a3 * g3;
     }
     for (; e < e1; ++e) s = s + val[e] * src(col[e]);
+    return s;
+}
+
+// The same sum over the sliced layout: entry k of this lane's row sits at e + 64 k.
+// The slice width w (a multiple of 4) is common to the wavefront, so the 64 lanes of
+// each load read consecutive addresses; entries k >= len are padding and are skipped,
+// so the row is added in CSR order exactly as row_dot does.
+template <class F>
+__device__ __forceinline__ double sliced_dot(const int32_t *__restrict__ col,
+                                             const double *__restrict__ val, int e, int w,
+                                             int len, F src) {
+    double s = 0.0;
+    for (int k = 0; k < w; k += 4, e += 4 * SLICE) {
+        const int c0 = col[e], c1 = col[e + SLICE], c2 = col[e + 2 * SLICE],
+                  c3 = col[e + 3 * SLICE];
+        const double a0 = val[e], a1 = val[e + SLICE], a2 = val[e + 2 * SLICE],
+                     a3 = val[e + 3 * SLICE];
+        const double g0 = src(c0), g1 = src(c1), g2 = src(c2), g3 = src(c3);
+        if (k < len) s = s + a0 * g0;
+        if (k + 1 < len) s = s + a1 * g1;
+        if (k + 2 < len) s = s + a2 * g2;
+        if (k + 3 < len) s = s + a3 * g3;
+    }
     return s;
 }
 
@@ -428,6 +458,8 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
         double *y = LDS ? smem + 3 * n : a.y + r0;
         const double *dvi = a.dscale ? a.dscale + v0 : nullptr;
         const double *dri = a.dscale ? a.dscale + a.ntot + r0 : nullptr;
+        const int32_t *sa_start = a.sa_start + a.sa_inst[id], *sa_width = a.sa_width + a.sa_inst[id];
+        const int32_t *sp_start = a.sp_start + a.sp_inst[id], *sp_width = a.sp_width + a.sp_inst[id];
         const int32_t *lra = a.lrA + a.lrA_off[id];
         const int nlra = a.lrA_off[id + 1] - a.lrA_off[id];
         const int32_t *lrp = a.lrP + a.lrP_off[id];
@@ -507,9 +539,11 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
                 const Step st = stp[sp];
                 // dual phase: y+ = proj_Y(y - d (A x~ - b)), y-bar averaging
                 for (int i = t; i < m; i += NT) {
-                    if (arp[i + 1] - arp[i] > LONG_ROW) continue;
-                    const double s = row_dot(a.a_col, a.a_val, arp[i], arp[i + 1],
-                                             [&](int cc) { return xt[cc]; });
+                    const int len = arp[i + 1] - arp[i];
+                    if (len > LONG_ROW) continue;
+                    const int sl = i / SLICE;
+                    const double s = sliced_dot(a.sa_col, a.sa_val, sa_start[sl] + i % SLICE,
+                                                sa_width[sl], len, [&](int cc) { return xt[cc]; });
                     double yn = y[i] - st.d * (s - b[i]);
                     if (rt[i] == 1 && yn < 0.0) yn = 0.0;
                     ybar[i] = (1.0 - st.w) * ybar[i] + st.w * yn;
@@ -533,10 +567,12 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
                 const double *xin = md ? xmd1 : xmd0;
                 double *xout = md ? xmd0 : xmd1;
                 for (int jj = t; jj < n; jj += NT) {
-                    if (prp[jj + 1] - prp[jj] > LONG_ROW) continue;
-                    const double s = row_dot(a.p_col, a.p_val, prp[jj], prp[jj + 1], [&](int cc) {
-                        return *(cc < n ? xin + cc : y + (cc - n));
-                    });
+                    const int len = prp[jj + 1] - prp[jj];
+                    if (len > LONG_ROW) continue;
+                    const int sl = jj / SLICE;
+                    const double s = sliced_dot(
+                        a.sp_col, a.sp_val, sp_start[sl] + jj % SLICE, sp_width[sl], len,
+                        [&](int cc) { return *(cc < n ? xin + cc : y + (cc - n)); });
                     primal_row(jj, s, st, c, l, u, x, xbar, xt, xout);
                 }
                 for (int q = 0; q < nlrp; ++q) {  // long rows: team-wide sum
@@ -763,11 +799,10 @@ __global__ __launch_bounds__(NT) void k_batch_norms(BatchDev a, int32_t maxit, d
     }
 }
 
-__global__ void k_queue_reset(int32_t *head, int64_t *clock0) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *head = 0;
-        *clock0 = (int64_t)wall_clock64();
-    }
+// resets the queue heads of all size classes and the solve's start clock
+__global__ void k_queue_reset(int32_t *head, int nhead, int64_t *clock0) {
+    if (threadIdx.x < nhead && blockIdx.x == 0) head[threadIdx.x] = 0;
+    if (threadIdx.x == 0 && blockIdx.x == 0) *clock0 = (int64_t)wall_clock64();
 }
 
 // ---------------------------------------------------------------------------
@@ -789,6 +824,8 @@ struct BatchData {
     std::vector<double> h_d;         // host copy of dscale (empty: not preconditioned)
     std::vector<double> h_c, h_b;    // the given c and b
     DevMem lrA_off, lrA, lrP_off, lrP;  // long-row lists (rows > LONG_ROW nonzeros)
+    DevMem sa_inst, sa_start, sa_width, sa_col, sa_val;  // sliced A (build_sliced)
+    DevMem sp_inst, sp_start, sp_width, sp_col, sp_val;  // sliced P
     std::vector<int32_t> order_off;  // offsets of each class in order_d
     std::vector<double> h_omega;     // staging of per-solve scalars (outlive async copies)
     std::vector<uint8_t> h_hx, h_hy;
@@ -796,6 +833,16 @@ struct BatchData {
     int num_cu = 256;
     int use_lds = 1;
     int32_t lds_need[NCLASS] = {0, 0, 0, 0};  // doubles of dynamic LDS per class
+    // one stream per size class (default priority), forked from and joined to `stream`
+    hipStream_t cls_stream[NCLASS] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[NCLASS] = {};
+    ~BatchData() {
+        for (int k = 0; k < NCLASS; ++k) {
+            if (cls_stream[k]) (void)hipStreamDestroy(cls_stream[k]);
+            if (ev_join[k]) (void)hipEventDestroy(ev_join[k]);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+    }
 };
 
 static int class_of(int64_t rows) {
@@ -850,7 +897,99 @@ static BatchDev make_dev(BatchData *bd) {
     a.lrP = bd->lrP.as<int32_t>();
     a.dscale = bd->h_d.empty() ? nullptr : bd->dscale.as<double>();
     a.ntot = bd->ntot;
+    a.sa_inst = bd->sa_inst.as<int32_t>();
+    a.sa_start = bd->sa_start.as<int32_t>();
+    a.sa_width = bd->sa_width.as<int32_t>();
+    a.sa_col = bd->sa_col.as<int32_t>();
+    a.sa_val = bd->sa_val.as<double>();
+    a.sp_inst = bd->sp_inst.as<int32_t>();
+    a.sp_start = bd->sp_start.as<int32_t>();
+    a.sp_width = bd->sp_width.as<int32_t>();
+    a.sp_col = bd->sp_col.as<int32_t>();
+    a.sp_val = bd->sp_val.as<double>();
     return a;
+}
+
+// Sliced copy of a batch CSR matrix (rows of all instances concatenated, off[B+1]
+// instance offsets) for the row loops of k_batch: each instance's rows are cut into
+// slices of SLICE rows, one row per lane of a wavefront; entry k of the row in lane l
+// of a slice sits at start[slice] + SLICE * k + l, so the lanes of a load read
+// consecutive addresses.  A slice's width is its longest row, rows longer than
+// LONG_ROW left out (the whole team sums those from the CSR arrays), rounded up to a
+// multiple of 4.  Padding holds column 0 and is never added.  src[e] is the CSR entry
+// copied to sliced position e (-1 for padding), so values can be gathered on the
+// device after preprocessing has scaled the CSR values.
+struct HostSliced {
+    std::vector<int32_t> inst, start, width, col;
+    std::vector<int64_t> src;
+};
+
+static int build_sliced(const std::vector<int32_t> &rp, const std::vector<int32_t> &col,
+                        const std::vector<int64_t> &off, int B, HostSliced &h) {
+    h.inst.assign(B + 1, 0);
+    int64_t pos = 0;
+    for (int i = 0; i < B; ++i) {
+        h.inst[i] = (int32_t)h.start.size();
+        for (int64_t r0 = off[i]; r0 < off[i + 1]; r0 += SLICE) {
+            const int64_t r1 = std::min<int64_t>(r0 + SLICE, off[i + 1]);
+            int64_t w = 0;
+            for (int64_t r = r0; r < r1; ++r) {
+                const int64_t len = rp[r + 1] - rp[r];
+                if (len <= LONG_ROW) w = std::max(w, len);
+            }
+            w = (w + 3) / 4 * 4;
+            if (pos + w * SLICE > INT32_MAX)
+                return fail(QP_ERR_INVALID_ARGUMENT, "batch too large for the sliced layout");
+            h.start.push_back((int32_t)pos);
+            h.width.push_back((int32_t)w);
+            pos += w * SLICE;
+        }
+    }
+    h.inst[B] = (int32_t)h.start.size();
+    h.col.assign((size_t)pos, 0);
+    h.src.assign((size_t)pos, -1);
+    for (int i = 0; i < B; ++i) {
+        int32_t sl = h.inst[i];
+        for (int64_t r0 = off[i]; r0 < off[i + 1]; r0 += SLICE, ++sl) {
+            const int64_t r1 = std::min<int64_t>(r0 + SLICE, off[i + 1]);
+            for (int64_t r = r0; r < r1; ++r) {
+                const int64_t len = rp[r + 1] - rp[r];
+                if (len > LONG_ROW) continue;
+                for (int64_t k = 0; k < len; ++k) {
+                    const int64_t e = h.start[sl] + SLICE * k + (r - r0);
+                    h.col[(size_t)e] = col[(size_t)(rp[r] + k)];
+                    h.src[(size_t)e] = rp[r] + k;
+                }
+            }
+        }
+    }
+    return QP_OK;
+}
+
+__global__ void k_sliced_gather(double *__restrict__ out, const double *__restrict__ val,
+                                const int64_t *__restrict__ src, int64_t len) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < len) out[e] = src[e] >= 0 ? val[src[e]] : 0.0;
+}
+
+// uploads the layout and gathers its values from the (possibly scaled) CSR values
+static int upload_sliced(const HostSliced &h, const double *csr_val, hipStream_t s,
+                         DevMem &inst, DevMem &start, DevMem &width, DevMem &col, DevMem &val) {
+    int rc;
+    DevMem src;
+    const int64_t len = (int64_t)h.col.size();
+    if ((rc = inst.upload(h.inst.data(), h.inst.size() * 4)) ||
+        (rc = start.upload(h.start.data(), h.start.size() * 4)) ||
+        (rc = width.upload(h.width.data(), h.width.size() * 4)) ||
+        (rc = col.upload(h.col.data(), h.col.size() * 4)) ||
+        (rc = src.upload(h.src.data(), h.src.size() * 8)) || (rc = val.alloc((size_t)len * 8 + 16)))
+        return rc;
+    if (len > 0)
+        hipLaunchKernelGGL(k_sliced_gather, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s,
+                           val.as<double>(), csr_val, src.as<int64_t>(), len);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return QP_OK;
 }
 
 template <class K>
@@ -863,15 +1002,14 @@ static int persistent_grid(K kernel, int nt, int count, int num_cu, size_t lds =
     return g < count ? g : count;
 }
 
-// launches one persistent kernel over the instances order[lo, hi)
+// launches one persistent kernel over the instances order[lo, hi) of size class k on
+// stream s, with queue head k (reset beforehand by run_classes)
 static void launch_class(BatchData *bd, BatchDev a, const DevSettings &ds, int nt, int lo, int hi,
-                         bool norms, int32_t maxit, double rtol) {
+                         int k, hipStream_t s, bool norms, int32_t maxit, double rtol) {
     a.order = bd->order_d.as<int32_t>() + lo;
     a.order_count = hi - lo;
     if (a.order_count <= 0) return;
-    hipStream_t s = bd->stream;
-    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, a.head,
-                       (int64_t *)bd->clock0.p);
+    a.head = bd->head.as<int32_t>() + k;
 #define QPB_LAUNCH(NT)                                                                           \
     do {                                                                                         \
         if (norms) {                                                                             \
@@ -895,9 +1033,30 @@ static void launch_class(BatchData *bd, BatchDev a, const DevSettings &ds, int n
     case 64: QPB_LAUNCH(64); break;
     case 128: QPB_LAUNCH(128); break;
     case 256: QPB_LAUNCH(256); break;
-    default: QPB_LAUNCH(512); break;
+    case 512: QPB_LAUNCH(512); break;
+    default: QPB_LAUNCH(1024); break;
     }
 #undef QPB_LAUNCH
+}
+
+// Runs launch(k, stream) for every size class, each on its own stream so that the
+// classes overlap: when the workgroups of one persistent launch run out of
+// instances they exit and the next class's workgroups take their place, instead of
+// the GPU idling behind one class's slowest instance.  The largest class starts
+// first (its instances are the longest per iteration).  The caller's stream waits
+// for all of them.
+template <class F>
+static int run_classes(BatchData *bd, F launch) {
+    hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, bd->stream, bd->head.as<int32_t>(),
+                       NCLASS, bd->clock0.as<int64_t>());
+    HIPCHK(hipEventRecord(bd->ev_fork, bd->stream));
+    for (int k = NCLASS - 1; k >= 0; --k) {
+        HIPCHK(hipStreamWaitEvent(bd->cls_stream[k], bd->ev_fork, 0));
+        launch(k, bd->cls_stream[k]);
+        HIPCHK(hipEventRecord(bd->ev_join[k], bd->cls_stream[k]));
+        HIPCHK(hipStreamWaitEvent(bd->stream, bd->ev_join[k], 0));
+    }
+    return QP_OK;
 }
 
 static DevSettings batch_settings(const qp_settings *s) {
@@ -1038,6 +1197,17 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
     BatchData *bd = new BatchData();
     bd->B = B;
     bd->stream = stream;
+    for (int k = 0; k < NCLASS; ++k) {
+        if (hipStreamCreateWithFlags(&bd->cls_stream[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&bd->ev_join[k], hipEventDisableTiming) != hipSuccess) {
+            delete bd;
+            return fail(QP_ERR_DEVICE, "batch: stream or event creation failed");
+        }
+    }
+    if (hipEventCreateWithFlags(&bd->ev_fork, hipEventDisableTiming) != hipSuccess) {
+        delete bd;
+        return fail(QP_ERR_DEVICE, "batch: event creation failed");
+    }
     bd->var_off.assign(d->var_off, d->var_off + B + 1);
     bd->row_off.assign(d->row_off, d->row_off + B + 1);
     const int64_t n = d->n, m = d->m;
@@ -1197,6 +1367,19 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
             us[j] = u[j] / bd->h_d[j];
         }
     }
+    {
+        HostSliced sa, sp;
+        std::vector<int64_t> voff(bd->var_off.begin(), bd->var_off.end());
+        std::vector<int64_t> roff(bd->row_off.begin(), bd->row_off.end());
+        if ((rc = build_sliced(ar, ac, roff, B, sa)) || (rc = build_sliced(pr, pc, voff, B, sp)) ||
+            (rc = upload_sliced(sa, bd->a_val.as<double>(), stream, bd->sa_inst, bd->sa_start,
+                                bd->sa_width, bd->sa_col, bd->sa_val)) ||
+            (rc = upload_sliced(sp, bd->p_val.as<double>(), stream, bd->sp_inst, bd->sp_start,
+                                bd->sp_width, bd->sp_col, bd->sp_val))) {
+            delete bd;
+            return rc;
+        }
+    }
     bd->h_c = c;
     bd->h_b = b;
     if ((rc = upload_vectors(bd, c, b)) || (rc = bd->l.upload(ls.data(), nb)) ||
@@ -1205,7 +1388,7 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
         (rc = bd->y.alloc(mb)) || (rc = bd->ybar.alloc(mb)) || (rc = bd->yrs.alloc(mb)) ||
         (rc = bd->x_out.alloc(nb)) || (rc = bd->y_out.alloc(mb)) || (rc = bd->x0.alloc(nb)) ||
         (rc = bd->y0.alloc(mb)) || (rc = bd->res.alloc((size_t)B * sizeof(State))) ||
-        (rc = bd->head.alloc(8)) || (rc = bd->clock0.alloc(8)) ||
+        (rc = bd->head.alloc(NCLASS * 8)) || (rc = bd->clock0.alloc(8)) ||
         (rc = bd->normA_d.alloc((size_t)B * 8)) || (rc = bd->normQ_d.alloc((size_t)B * 8)) ||
         (rc = bd->b_inf_d.alloc((size_t)B * 8)) || (rc = bd->c_inf_d.alloc((size_t)B * 8)) ||
         (rc = bd->omega0_d.alloc((size_t)B * 8)) || (rc = bd->has_x0.alloc((size_t)B)) ||
@@ -1266,9 +1449,14 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
     } else {
         BatchDev a = make_dev(bd);
         DevSettings ds = batch_settings(s);
-        for (int k = 0; k < NCLASS; ++k)
-            launch_class(bd, a, ds, bd->threads[k], bd->order_off[k], bd->order_off[k + 1], true,
-                         s->power_iter_max, s->power_iter_rtol);
+        rc = run_classes(bd, [&](int k, hipStream_t cs) {
+            launch_class(bd, a, ds, bd->threads[k], bd->order_off[k], bd->order_off[k + 1], k, cs,
+                         true, s->power_iter_max, s->power_iter_rtol);
+        });
+        if (rc) {
+            delete bd;
+            return rc;
+        }
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) {
             delete bd;
@@ -1335,8 +1523,9 @@ int batch_update_vectors(BatchData *bd, const double *c, const double *bvec, int
 int batch_set_threads(BatchData *b, const int32_t *threads) {
     for (int k = 0; k < NCLASS; ++k) {
         const int32_t v = threads[k];
-        if (v != 64 && v != 128 && v != 256 && v != 512)
-            return fail(QP_ERR_INVALID_ARGUMENT, "threads per instance must be 64, 128, 256 or 512");
+        if (v != 64 && v != 128 && v != 256 && v != 512 && v != 1024)
+            return fail(QP_ERR_INVALID_ARGUMENT,
+                        "threads per instance must be 64, 128, 256, 512 or 1024");
     }
     std::memcpy(b->threads, threads, sizeof(b->threads));
     return QP_OK;
@@ -1395,12 +1584,14 @@ static int run_batch(BatchData *bd, const qp_settings *s, int ms, const qp_warm_
                            ? (int64_t)(s->time_limit_s * 1000.0 * (double)bd->wall_khz)
                            : 0;
     DevSettings ds = batch_settings(s);
-    for (int k = 0; k < NCLASS; ++k) {
+    int rc = run_classes(bd, [&](int k, hipStream_t cs) {
         int lo = bd->order_off[k], hi = bd->order_off[k + 1];
         if (max_count && max_count[k] >= 0 && hi - lo > max_count[k]) hi = lo + max_count[k];
-        a.lds_doubles = bd->use_lds ? bd->lds_need[k] : 0;
-        launch_class(bd, a, ds, threads[k], lo, hi, false, 0, 0.0);
-    }
+        BatchDev ak = a;
+        ak.lds_doubles = bd->use_lds ? bd->lds_need[k] : 0;
+        launch_class(bd, ak, ds, threads[k], lo, hi, k, cs, false, 0, 0.0);
+    });
+    if (rc) return rc;
     HIPCHK(hipGetLastError());
     return QP_OK;
 }
@@ -1463,7 +1654,7 @@ int batch_autotune(BatchData *bd, const qp_settings *s, int32_t sample, int32_t 
     for (int k = 0; k < NCLASS; ++k) {
         if (bd->order_off[k + 1] == bd->order_off[k]) continue;
         float best_ms = 1e30f;
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NCHOICE; ++c) {
             int32_t thr[NCLASS], cnt[NCLASS];
             for (int q = 0; q < NCLASS; ++q) {
                 thr[q] = THREAD_CHOICES[c];

@@ -137,12 +137,12 @@ def test_batch_team_sizes_agree(orc, qpa):
     ref = _oracle_all(orc, insts, eps=1e-6)
     bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6))
     bs.set_norms([r[3] for r in ref], [r[4] for r in ref])
-    for t in (64, 128, 256, 512):
+    for t in (64, 128, 256, 512, 1024):
         bs.set_threads([t] * 4)
         xg, yg, rg = bs.solve()
         _compare(batch, xg, yg, rg, ref)
     chosen = bs.autotune(sample=8, iters=64)
-    assert all(c in (64, 128, 256, 512) for c in chosen)
+    assert all(c in (64, 128, 256, 512, 1024) for c in chosen)
     xg, yg, rg = bs.solve()
     _compare(batch, xg, yg, rg, ref)
     bs.close()
