@@ -537,6 +537,14 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
             const int64_t k0 = S.k;
             for (int j = 0; j < len; ++j) {
                 const Step st = stp[sp];
+                // the next iteration's step depends only on omega and k: the team's last
+                // thread (the one with the fewest rows) computes it while the others work,
+                // into the slot nobody reads before the two barriers below
+                if (t == NT - 1) {
+                    double sl = s_last;
+                    stp[sp ^ 1] = make_step(ds, S.omega, k0 + j + 1, &sl);
+                    s_last = sl;
+                }
                 // dual phase: y+ = proj_Y(y - d (A x~ - b)), y-bar averaging
                 for (int i = t; i < m; i += NT) {
                     const int len = arp[i + 1] - arp[i];
@@ -585,11 +593,6 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
                     }
                     team_sum<NT, 1>(sv, red);
                     if (t == 0) primal_row(jj, sv[0], st, c, l, u, x, xbar, xt, xout);
-                }
-                if (t == 0) {
-                    double sl = s_last;
-                    stp[sp ^ 1] = make_step(ds, S.omega, k0 + j + 1, &sl);
-                    s_last = sl;
                 }
                 __syncthreads();
                 sp ^= 1;
