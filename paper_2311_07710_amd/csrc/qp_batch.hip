@@ -447,15 +447,19 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
         const int32_t *prp = a.p_rowptr + v0;
         const double *c = a.c + v0, *l = a.l + v0, *u = a.u + v0, *b = a.b + r0;
         const uint8_t *rt = a.rt + r0;
-        double *x = a.x + v0, *xbar = a.xbar + v0, *xrs = a.xrs + v0;
-        double *ybar = a.ybar + r0, *yrs = a.yrs + r0;
-        // the gathered vectors (x~ in the dual phase, x_md and y in the primal
-        // phase) live in LDS when the instance fits, else in HBM
-        double *xt = LDS ? smem : a.xt + v0;
+        double *xrs = a.xrs + v0, *yrs = a.yrs + r0;
+        // The vectors every iteration reads and writes live in LDS when the instance
+        // fits (x~ | x_md[0] | x_md[1] | x | x-bar | y | y-bar: 5 n + 2 m doubles), else in
+        // HBM.  In LDS, neither the gathers nor the epilogues touch global memory, and
+        // the barriers between the phases wait for no global stores.
         // (named pointers, not an array indexed at run time, so LDS stays visible)
+        double *xt = LDS ? smem : a.xt + v0;
         double *const xmd0 = LDS ? smem + n : a.xmd0 + v0;
         double *const xmd1 = LDS ? smem + 2 * n : a.xmd1 + v0;
-        double *y = LDS ? smem + 3 * n : a.y + r0;
+        double *x = LDS ? smem + 3 * n : a.x + v0;
+        double *xbar = LDS ? smem + 4 * n : a.xbar + v0;
+        double *y = LDS ? smem + 5 * n : a.y + r0;
+        double *ybar = LDS ? smem + 5 * n + m : a.ybar + r0;
         const double *dvi = a.dscale ? a.dscale + v0 : nullptr;
         const double *dri = a.dscale ? a.dscale + a.ntot + r0 : nullptr;
         const int32_t *sa_start = a.sa_start + a.sa_inst[id], *sa_width = a.sa_width + a.sa_inst[id];
@@ -642,7 +646,7 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
-    extern __shared__ double smem[];  // x~ | x_md[0] | x_md[1] | y when they fit
+    extern __shared__ double smem[];  // x~ | x_md[0] | x_md[1] | x | x-bar | y | y-bar when they fit
     __shared__ int s_q;
     __shared__ State S;
     __shared__ Step stp[2];
@@ -655,7 +659,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
         if (q >= a.order_count) break;
         const int id = a.order[q];
         const int n = a.var_off[id + 1] - a.var_off[id], m = a.row_off[id + 1] - a.row_off[id];
-        if (3 * n + m <= a.lds_doubles)
+        if (5 * n + 2 * m <= a.lds_doubles)
             solve_instance<NT, true>(a, base, id, smem, S, stp, red, s_last);
         else
             solve_instance<NT, false>(a, base, id, smem, S, stp, red, s_last);
@@ -1427,16 +1431,16 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
     int dev = 0;
     (void)hipGetDevice(&dev);
     {
-        // dynamic LDS per class: the largest 3 n_i + m_i that fits the cap
+        // dynamic LDS per class: the largest 5 n_i + 2 m_i doubles that fit the cap
         int max_lds = 65536;
         (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        const int cap = std::min(max_lds, 160 * 1024) - 4096;  // room for the static LDS
+        const int cap = std::min(max_lds, 160 * 1024) - 8192;  // room for the static LDS
         for (int k = 0; k < NCLASS; ++k) {
             int64_t need = 0;
             for (int32_t id : bd->order[k]) {
                 const int64_t nv = bd->var_off[id + 1] - bd->var_off[id];
                 const int64_t mv = bd->row_off[id + 1] - bd->row_off[id];
-                const int64_t w = 3 * nv + mv;
+                const int64_t w = 5 * nv + 2 * mv;
                 if (w * 8 <= cap) need = std::max(need, w);
             }
             bd->lds_need[k] = (int32_t)need;
