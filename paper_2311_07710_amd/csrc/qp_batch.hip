@@ -408,20 +408,35 @@ __device__ __attribute__((noinline)) void batch_decide(int mode, const double *r
     decide_update(mode, ra, rp, *S, *ds, len);
 }
 
-// projected primal step, x-bar averaging and the next x~ / x_md of row j
-__device__ __forceinline__ void primal_row(int j, double s, const Step &st, const double *c,
-                                           const double *l, const double *u, double *x,
-                                           double *xbar, double *xt, double *xout) {
-    const double g = s + c[j];
-    const double xo = x[j];
-    double xn = xo - st.p * g;
-    if (xn < l[j]) xn = l[j];
-    if (xn > u[j]) xn = u[j];
-    const double xb = (1.0 - st.w) * xbar[j] + st.w * xn;
+// projected primal step and x-bar averaging of one row (row sum s, c_j, l_j, u_j,
+// x_j, x-bar_j): the new x_j and x-bar_j
+__device__ __forceinline__ void primal_update(double s, const Step &st, double cj, double lj,
+                                              double uj, double xo, double xbo, double &xn,
+                                              double &xb) {
+    const double g = s + cj;
+    xn = xo - st.p * g;
+    if (xn < lj) xn = lj;
+    if (xn > uj) xn = uj;
+    xb = (1.0 - st.w) * xbo + st.w * xn;
+}
+
+// the row's outputs: x, x-bar and the next x~ / x_md
+__device__ __forceinline__ void primal_store(int j, const Step &st, double xo, double xn,
+                                             double xb, double *x, double *xbar, double *xt,
+                                             double *xout) {
     x[j] = xn;
     xbar[j] = xb;
     xt[j] = xn + st.theta_next * (xn - xo);
     xout[j] = (1.0 - st.w_next) * xb + st.w_next * xn;
+}
+
+__device__ __forceinline__ void primal_row(int j, double s, const Step &st, const double *c,
+                                           const double *l, const double *u, double *x,
+                                           double *xbar, double *xt, double *xout) {
+    const double xo = x[j];
+    double xn, xb;
+    primal_update(s, st, c[j], l[j], u[j], xo, xbar[j], xn, xb);
+    primal_store(j, st, xo, xn, xb, x, xbar, xt, xout);
 }
 
 __device__ __forceinline__ double proj_box_b(double v, double lo, double hi) {
@@ -551,15 +566,26 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
                 }
                 // dual phase: y+ = proj_Y(y - d (A x~ - b)), y-bar averaging
                 for (int i = t; i < m; i += NT) {
+                    // Every load the row needs is issued before any result is used:
+                    // the slice's start and width (the slice is the wavefront's, so
+                    // these are scalar loads), the row pointers and the epilogue's
+                    // operands.  The row's results are computed unconditionally and only
+                    // the stores depend on the row being short (long rows: team loop).
+                    const int sl = __builtin_amdgcn_readfirstlane(i / SLICE);
+                    const int e = sa_start[sl] + i % SLICE, w = sa_width[sl];
                     const int len = arp[i + 1] - arp[i];
-                    if (len > LONG_ROW) continue;
-                    const int sl = i / SLICE;
-                    const double s = sliced_dot(a.sa_col, a.sa_val, sa_start[sl] + i % SLICE,
-                                                sa_width[sl], len, [&](int cc) { return xt[cc]; });
-                    double yn = y[i] - st.d * (s - b[i]);
-                    if (rt[i] == 1 && yn < 0.0) yn = 0.0;
-                    ybar[i] = (1.0 - st.w) * ybar[i] + st.w * yn;
-                    y[i] = yn;
+                    const double bi = b[i];
+                    const uint8_t ti = rt[i];
+                    const bool mine = len <= LONG_ROW;
+                    const double s = sliced_dot(a.sa_col, a.sa_val, e, mine ? w : 0, len,
+                                                [&](int cc) { return xt[cc]; });
+                    double yn = y[i] - st.d * (s - bi);
+                    if (ti == 1 && yn < 0.0) yn = 0.0;
+                    const double ybn = (1.0 - st.w) * ybar[i] + st.w * yn;
+                    if (mine) {
+                        ybar[i] = ybn;
+                        y[i] = yn;
+                    }
                 }
                 for (int q = 0; q < nlra; ++q) {  // long rows: team-wide sum
                     const int i = lra[q];
@@ -579,13 +605,19 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
                 const double *xin = md ? xmd1 : xmd0;
                 double *xout = md ? xmd0 : xmd1;
                 for (int jj = t; jj < n; jj += NT) {
+                    // loads first, stores predicated (as in the dual phase)
+                    const int sl = __builtin_amdgcn_readfirstlane(jj / SLICE);
+                    const int e = sp_start[sl] + jj % SLICE, w = sp_width[sl];
                     const int len = prp[jj + 1] - prp[jj];
-                    if (len > LONG_ROW) continue;
-                    const int sl = jj / SLICE;
+                    const double cj = c[jj], lj = l[jj], uj = u[jj];
+                    const bool mine = len <= LONG_ROW;
                     const double s = sliced_dot(
-                        a.sp_col, a.sp_val, sp_start[sl] + jj % SLICE, sp_width[sl], len,
+                        a.sp_col, a.sp_val, e, mine ? w : 0, len,
                         [&](int cc) { return *(cc < n ? xin + cc : y + (cc - n)); });
-                    primal_row(jj, s, st, c, l, u, x, xbar, xt, xout);
+                    const double xo = x[jj];
+                    double xn, xb;
+                    primal_update(s, st, cj, lj, uj, xo, xbar[jj], xn, xb);
+                    if (mine) primal_store(jj, st, xo, xn, xb, x, xbar, xt, xout);
                 }
                 for (int q = 0; q < nlrp; ++q) {  // long rows: team-wide sum
                     const int jj = lrp[q];
