@@ -231,7 +231,7 @@ int qp_set_norms(qp_handle *h, const double *norm_A, const double *norm_Q);
 
 /* Batch handles: instances are grouped in four size classes by n_i + m_i
  * (<= 256, <= 1024, <= 2048, larger), each solved by a team of 64, 128, 256, 512 or
- * 1024 threads (1-16 wavefronts) per instance.  qp_batch_autotune times every team size
+ * 1024 threads (1-16 wavefronts) per instance (256, 1024, 1024, 1024 until changed).  qp_batch_autotune times every team size
  * on up to `sample` instances of each class for `iters` iterations and keeps the
  * fastest; threads_out[4] (nullable) receives the choice.  qp_batch_set_threads
  * sets the four team sizes directly.  Both return QP_ERR_BATCH_MISMATCH on a

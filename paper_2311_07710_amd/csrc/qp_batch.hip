@@ -445,12 +445,24 @@ __device__ __forceinline__ double proj_box_b(double v, double lo, double hi) {
     return v;
 }
 
-// One instance, start to finish, by the whole team.  LDS says whether the gathered
-// vectors (x~, the x_md ping-pong pair, y) live in LDS.  As a compile-time flag it lets
-// every access to them compile to LDS instructions; chosen at run time through one
-// pointer, they became generic (flat) accesses, which pay vector-memory latency even
-// when the address is in LDS.
-template <int NT, bool LDS>
+// LDS residency of an instance's vectors
+enum LdsMode {
+    LDS_NONE = 0,      // all vectors in HBM
+    LDS_GATHERED = 1,  // x~ | x_md[0] | x_md[1] | y  (3 n + m doubles)
+    LDS_ALL = 2,       // x~ | x_md[0] | x_md[1] | x | x-bar | y | y-bar  (5 n + 2 m doubles)
+};
+
+__host__ __device__ inline int lds_mode_of(int64_t n, int64_t m, int64_t lds_doubles) {
+    if (5 * n + 2 * m <= lds_doubles) return LDS_ALL;
+    if (3 * n + m <= lds_doubles) return LDS_GATHERED;
+    return LDS_NONE;
+}
+
+// One instance, start to finish, by the whole team.  MODE says which vectors live in
+// LDS.  As a compile-time parameter it lets every access to them compile to LDS
+// instructions; chosen at run time through one pointer, they became generic (flat)
+// accesses, which pay vector-memory latency even when the address is in LDS.
+template <int NT, int MODE>
 __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSettings &base,
                                                int id, double *smem, State &S, Step *stp,
                                                double *red, double &s_last) {
@@ -463,18 +475,19 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
         const double *c = a.c + v0, *l = a.l + v0, *u = a.u + v0, *b = a.b + r0;
         const uint8_t *rt = a.rt + r0;
         double *xrs = a.xrs + v0, *yrs = a.yrs + r0;
-        // The vectors every iteration reads and writes live in LDS when the instance
-        // fits (x~ | x_md[0] | x_md[1] | x | x-bar | y | y-bar: 5 n + 2 m doubles), else in
-        // HBM.  In LDS, neither the gathers nor the epilogues touch global memory, and
-        // the barriers between the phases wait for no global stores.
+        // The vectors every iteration reads and writes live in LDS as far as the
+        // instance fits: with all of them there (LDS_ALL) neither the gathers nor the
+        // epilogues touch global memory and the barriers between the phases wait for
+        // no global stores; LDS_GATHERED keeps only the gathered ones.
         // (named pointers, not an array indexed at run time, so LDS stays visible)
-        double *xt = LDS ? smem : a.xt + v0;
-        double *const xmd0 = LDS ? smem + n : a.xmd0 + v0;
-        double *const xmd1 = LDS ? smem + 2 * n : a.xmd1 + v0;
-        double *x = LDS ? smem + 3 * n : a.x + v0;
-        double *xbar = LDS ? smem + 4 * n : a.xbar + v0;
-        double *y = LDS ? smem + 5 * n : a.y + r0;
-        double *ybar = LDS ? smem + 5 * n + m : a.ybar + r0;
+        constexpr bool G = MODE != LDS_NONE, ALL = MODE == LDS_ALL;
+        double *xt = G ? smem : a.xt + v0;
+        double *const xmd0 = G ? smem + n : a.xmd0 + v0;
+        double *const xmd1 = G ? smem + 2 * n : a.xmd1 + v0;
+        double *x = ALL ? smem + 3 * n : a.x + v0;
+        double *xbar = ALL ? smem + 4 * n : a.xbar + v0;
+        double *y = ALL ? smem + 5 * n : G ? smem + 3 * n : a.y + r0;
+        double *ybar = ALL ? smem + 5 * n + m : a.ybar + r0;
         const double *dvi = a.dscale ? a.dscale + v0 : nullptr;
         const double *dri = a.dscale ? a.dscale + a.ntot + r0 : nullptr;
         const int32_t *sa_start = a.sa_start + a.sa_inst[id], *sa_width = a.sa_width + a.sa_inst[id];
@@ -678,7 +691,7 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
-    extern __shared__ double smem[];  // x~ | x_md[0] | x_md[1] | x | x-bar | y | y-bar when they fit
+    extern __shared__ double smem[];  // the LDS-resident vectors (LdsMode)
     __shared__ int s_q;
     __shared__ State S;
     __shared__ Step stp[2];
@@ -691,10 +704,13 @@ __global__ __launch_bounds__(NT) void k_batch(BatchDev a, DevSettings base) {
         if (q >= a.order_count) break;
         const int id = a.order[q];
         const int n = a.var_off[id + 1] - a.var_off[id], m = a.row_off[id + 1] - a.row_off[id];
-        if (5 * n + 2 * m <= a.lds_doubles)
-            solve_instance<NT, true>(a, base, id, smem, S, stp, red, s_last);
+        const int mode = lds_mode_of(n, m, a.lds_doubles);
+        if (mode == LDS_ALL)
+            solve_instance<NT, LDS_ALL>(a, base, id, smem, S, stp, red, s_last);
+        else if (mode == LDS_GATHERED)
+            solve_instance<NT, LDS_GATHERED>(a, base, id, smem, S, stp, red, s_last);
         else
-            solve_instance<NT, false>(a, base, id, smem, S, stp, red, s_last);
+            solve_instance<NT, LDS_NONE>(a, base, id, smem, S, stp, red, s_last);
         __syncthreads();
     }
 }
@@ -855,7 +871,9 @@ struct BatchData {
     std::vector<double> normA, normQ, c_norm2, b_norm2, c_inf, b_inf;
     std::vector<int32_t> cls;                 // size class of each instance
     std::vector<std::vector<int32_t>> order;  // per class, by decreasing work
-    int32_t threads[NCLASS] = {64, 128, 256, 512};
+    // team size per class until qp_batch_autotune / qp_batch_set_threads: what the
+    // autotuner chooses on uneven MPC batches (larger teams shorten the slowest solves)
+    int32_t threads[NCLASS] = {256, 1024, 1024, 1024};
     DevMem var_off_d, row_off_d, a_rowptr, a_col, a_val, p_rowptr, p_col, p_val;
     DevMem c, b, l, u, rt, normA_d, normQ_d, b_inf_d, c_inf_d, omega0_d, has_x0, has_y0, x0, y0;
     DevMem x, xbar, xt, xmd0, xmd1, xrs, y, ybar, yrs, x_out, y_out, res, order_d, head, clock0;
@@ -1463,7 +1481,7 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
     int dev = 0;
     (void)hipGetDevice(&dev);
     {
-        // dynamic LDS per class: the largest 5 n_i + 2 m_i doubles that fit the cap
+        // dynamic LDS per class: the most any instance can use (LdsMode) within the cap
         int max_lds = 65536;
         (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         const int cap = std::min(max_lds, 160 * 1024) - 8192;  // room for the static LDS
@@ -1472,8 +1490,11 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
             for (int32_t id : bd->order[k]) {
                 const int64_t nv = bd->var_off[id + 1] - bd->var_off[id];
                 const int64_t mv = bd->row_off[id + 1] - bd->row_off[id];
-                const int64_t w = 5 * nv + 2 * mv;
-                if (w * 8 <= cap) need = std::max(need, w);
+                const int64_t cap_d = cap / 8;
+                const int mode = lds_mode_of(nv, mv, cap_d);
+                const int64_t w = mode == LDS_ALL ? 5 * nv + 2 * mv
+                                  : mode == LDS_GATHERED ? 3 * nv + mv : 0;
+                need = std::max(need, w);
             }
             bd->lds_need[k] = (int32_t)need;
         }
