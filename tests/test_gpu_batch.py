@@ -217,3 +217,44 @@ def test_batch_full_size_sampled(orc, qpa):
         zo = np.concatenate([xo, yo])
         zg = np.concatenate([xg[v0:v1], yg[r0:r1]])
         assert np.max(np.abs(zg - zo)) <= 1e-8 * (1 + np.max(np.abs(zo)))
+
+
+def _slice_edge_instance(seed=21, n=200, m=300):
+    """Rows around the 128-entry long-row limit (127, 128, 129) in A and in P (a
+    column of A with 231 entries, one with about 120), an all-empty 64-row slice
+    (rows 64-127) and a partial last slice (rows 256-299)."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((m, n))
+    for i, L in enumerate((127, 128, 129, 0, 1)):
+        A[i, rng.choice(n, L, replace=False)] = rng.standard_normal(L)
+    live = [i for i in range(5, m) if not 64 <= i < 128]
+    for i in live:
+        A[i, rng.choice(np.arange(2, n), 3, replace=False)] = rng.standard_normal(3)
+    A[live, 0] = rng.standard_normal(len(live))              # P row 0: > 128 entries
+    A[np.array(live[:118]), 1] = rng.standard_normal(118)      # P row 1: about 120
+    Q = np.diag(rng.uniform(0.5, 2.0, n))
+    l, u = np.full(n, -2.0), np.full(n, 2.0)
+    xf = rng.uniform(-1.0, 1.0, n)
+    row_type = np.where(np.arange(m) % 2 == 0, qpgen.instances.EQ, qpgen.instances.GE)
+    ax = A @ xf
+    b = np.where(row_type == qpgen.instances.EQ, ax, ax - rng.uniform(0.0, 1.0, m))
+    return qp_refs.make_qp(Q, A, rng.standard_normal(n), b, l, u, row_type, name="slice_edges")
+
+
+def test_batch_sliced_layout_edges(orc, qpa):
+    """The sliced row layout at its edges, next to instances of other size classes."""
+    edge = _slice_edge_instance()
+    lens_a = np.diff(edge.a_rowptr)
+    assert {127, 128, 129}.issubset(set(lens_a.tolist())) and (lens_a[64:128] == 0).all()
+    P_lens = np.diff(edge.q_rowptr) + np.bincount(edge.a_col, minlength=edge.n)
+    assert P_lens.max() > 128 and ((P_lens > 64) & (P_lens <= 128)).any()
+    insts = [edge, qpgen.tiny_random_qp(4), _mixed_batch()[3]]
+    batch = qpgen.concat_batch(insts)
+    ref = _oracle_all(orc, insts, eps=1e-6, max_iter=4000)   # the edge instance stops at the cap
+    for threads in (64, 1024):
+        bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6, max_iter=4000))
+        bs.set_norms([r[3] for r in ref], [r[4] for r in ref])
+        bs.set_threads([threads] * 4)
+        xg, yg, rg = bs.solve()
+        bs.close()
+        _compare(batch, xg, yg, rg, ref)
