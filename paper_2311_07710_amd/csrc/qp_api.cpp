@@ -832,19 +832,22 @@ void enqueue_kkt(qp_handle *h, hipStream_t s, State *st, int32_t *sa, int32_t *s
     }
 }
 
-void enqueue_interval(qp_handle *h, const DevSettings &ds, int md_in, int len, bool timed) {
+// ev: with profiling, 3 events per iteration (before the dual phase, between the
+// phases, after the primal phase); nullptr otherwise
+void enqueue_interval(qp_handle *h, const DevSettings &ds, int md_in, int len,
+                      hipEvent_t *ev) {
     hipStream_t s = h->stream;
     const Step *tab = h->table.as<Step>();
     State *st = h->state.as<State>();
     int md = md_in;
     for (int j = 0; j < len; ++j) {
-        if (timed) (void)hipEventRecord(h->prof_ev[4 * j + 0], s);
+        if (ev) (void)hipEventRecord(ev[3 * j + 0], s);
         if (h->npA > 1) launch_dual_panels(s, h->panA.view, h->vecs, h->n, tab + j, st);
         else launch_dual(s, h->partA.view, h->A, h->vecs, tab + j, st);
-        if (timed) (void)hipEventRecord(h->prof_ev[4 * j + 1], s);
+        if (ev) (void)hipEventRecord(ev[3 * j + 1], s);
         if (h->npP > 1) launch_primal_panels(s, h->panP.view, h->vecs, md, h->n, tab + j, st);
         else launch_primal(s, h->partP.view, h->P, h->vecs, md, tab + j, st, h->n);
-        if (timed) (void)hipEventRecord(h->prof_ev[4 * j + 2], s);
+        if (ev) (void)hipEventRecord(ev[3 * j + 2], s);
         md ^= 1;
     }
     int32_t sa, sp;
@@ -871,7 +874,7 @@ int get_graph(qp_handle *h, const DevSettings &ds, int md_in, hipGraphExec_t *ou
     if (!h->graph[md_in]) {
         hipGraph_t g;
         HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_interval(h, ds, md_in, ds.interval, false);
+        enqueue_interval(h, ds, md_in, ds.interval, nullptr);
         HIPCHK(hipStreamEndCapture(h->stream, &g));
         hipError_t e = hipGraphInstantiate(&h->graph[md_in], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -1073,9 +1076,11 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
     h->log.clear();
     h->prof = qp_profile{};
     h->prof.dual_bytes = 0.0;
-    if (profile && (int)h->prof_ev.size() < 4 * L) {
+    // profiling: two event sets of 3 per iteration, alternating between intervals, so
+    // one interval stays in flight while the previous one is read (as without profiling)
+    if (profile && (int)h->prof_ev.size() < 6 * L) {
         for (auto &e : h->prof_ev) (void)hipEventDestroy(e);
-        h->prof_ev.assign(4 * L, nullptr);
+        h->prof_ev.assign(6 * L, nullptr);
         for (auto &e : h->prof_ev) HIPCHK(hipEventCreate(&e));
     }
 
@@ -1134,18 +1139,25 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
     int64_t enqueued = 0;
     int md = 0;
     int slot = 0;
-    std::deque<std::pair<int, int>> inflight;  // (ring slot, interval length)
+    struct Inflight {
+        int slot, len, evset;  // ring slot, interval length, profiling event set
+    };
+    std::deque<Inflight> inflight;
+    int evset = 0;
     bool stop = last.done != 0;
     bool time_up = false;
     int32_t seen_checks = 0;
-    auto process = [&](int sl, int len) -> int {
+    auto process = [&](const Inflight &f) -> int {
+        const int sl = f.slot, len = f.len;
         HIPCHK(hipEventSynchronize(h->ring_ev[sl]));
         const State &S = h->h_state[sl];
-        if (profile) {
+        // an interval enqueued after the solve ended ran as no-ops: not timed
+        if (profile && !last.done) {
+            const hipEvent_t *ev = h->prof_ev.data() + (size_t)f.evset * 3 * L;
             for (int j = 0; j < len; ++j) {
                 float a = 0.f, b = 0.f;
-                HIPCHK(hipEventElapsedTime(&a, h->prof_ev[4 * j + 0], h->prof_ev[4 * j + 1]));
-                HIPCHK(hipEventElapsedTime(&b, h->prof_ev[4 * j + 1], h->prof_ev[4 * j + 2]));
+                HIPCHK(hipEventElapsedTime(&a, ev[3 * j + 0], ev[3 * j + 1]));
+                HIPCHK(hipEventElapsedTime(&b, ev[3 * j + 1], ev[3 * j + 2]));
                 h->prof.dual_ms += a;
                 h->prof.primal_ms += b;
             }
@@ -1179,26 +1191,28 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
             if ((rc = get_graph(h, ds, md, &g))) return rc;
             HIPCHK(hipGraphLaunch(g, s));
         } else {
-            enqueue_interval(h, ds, md, len, profile);
+            enqueue_interval(h, ds, md, len,
+                             profile ? h->prof_ev.data() + (size_t)evset * 3 * L : nullptr);
         }
         md = (md + len) & 1;
         enqueued += len;
         HIPCHK(hipMemcpyAsync(&h->h_state[slot], st, sizeof(State), hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(h->ring_ev[slot], s));
-        inflight.emplace_back(slot, len);
+        inflight.push_back(Inflight{slot, len, evset});
         slot = (slot + 1) % qp_handle::RING;
-        // profiling reuses one event set per interval: drain before the next one
-        const size_t depth = profile ? 0 : 1;
-        while (inflight.size() > depth) {
-            auto [sl, ln] = inflight.front();
+        evset ^= 1;
+        // one interval in flight while the previous one is read (with profiling, its
+        // event set is the other one of the two)
+        while (inflight.size() > 1) {
+            const Inflight f = inflight.front();
             inflight.pop_front();
-            if ((rc = process(sl, ln))) return rc;
+            if ((rc = process(f))) return rc;
         }
     }
     while (!inflight.empty()) {
-        auto [sl, ln] = inflight.front();
+        const Inflight f = inflight.front();
         inflight.pop_front();
-        if ((rc = process(sl, ln))) return rc;
+        if ((rc = process(f))) return rc;
     }
     HIPCHK(hipStreamSynchronize(s));
     if (!last.done) last.status = time_up ? QP_TIME_LIMIT : QP_ITERATION_LIMIT;
