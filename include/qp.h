@@ -123,8 +123,9 @@ typedef struct {
     int32_t warm_fallback;   /* 1 (default): a warm start is used only if its relKKT is
                                 below that of the cold start */
     int32_t use_graph;       /* 1 (default): replay one captured hipGraph per check interval */
-    int32_t profile;         /* 1: time every dual/primal kernel launch with hipEvents
-                                (direct launches, no graph); read with qp_get_profile */
+    int32_t profile;         /* k >= 1: time the dual and primal phases of every k-th
+                                iteration with hipEvents (direct launches, no graph);
+                                read with qp_get_profile; 0 (default): off */
     int32_t log_checks;      /* 1: record one qp_check_info per evaluation (qp_get_check_log) */
     int32_t device;          /* HIP device ordinal; default 0 */
     int32_t panels_dual;     /* column panels of A for the dual phase: 0 = automatic (4 when
@@ -191,8 +192,8 @@ typedef struct {
 } qp_check_info;
 
 typedef struct {
-    int64_t dual_launches, primal_launches;
-    double dual_ms, primal_ms;     /* summed hipEvent durations */
+    int64_t dual_launches, primal_launches;  /* phases timed */
+    double dual_ms, primal_ms;     /* summed hipEvent durations of the timed phases */
     double dual_bytes, primal_bytes; /* algorithmic HBM bytes of ONE launch */
 } qp_profile;
 

@@ -443,6 +443,7 @@ int check_settings(const qp_settings &s) {
     if (!(s.step_safety > 0.0)) return fail(QP_ERR_INVALID_ARGUMENT, "step_safety must be > 0");
     if (s.momentum != 0 && s.momentum != 1)
         return fail(QP_ERR_INVALID_ARGUMENT, "momentum must be 0 or 1");
+    if (s.profile < 0) return fail(QP_ERR_INVALID_ARGUMENT, "profile must be >= 0");
     if (s.precondition != 0 && s.precondition != 1)
         return fail(QP_ERR_INVALID_ARGUMENT, "precondition must be 0 or 1");
     if (s.ruiz_iters < 0 || s.ruiz_iters > 100)
@@ -832,22 +833,24 @@ void enqueue_kkt(qp_handle *h, hipStream_t s, State *st, int32_t *sa, int32_t *s
     }
 }
 
-// ev: with profiling, 3 events per iteration (before the dual phase, between the
-// phases, after the primal phase); nullptr otherwise
+// ev: with profiling, 3 events per timed iteration (before the dual phase, between
+// the phases, after the primal phase) for iterations j with j % stride == 0;
+// nullptr otherwise
 void enqueue_interval(qp_handle *h, const DevSettings &ds, int md_in, int len,
-                      hipEvent_t *ev) {
+                      hipEvent_t *ev, int stride) {
     hipStream_t s = h->stream;
     const Step *tab = h->table.as<Step>();
     State *st = h->state.as<State>();
     int md = md_in;
     for (int j = 0; j < len; ++j) {
-        if (ev) (void)hipEventRecord(ev[3 * j + 0], s);
+        const bool timed = ev && j % stride == 0;
+        if (timed) (void)hipEventRecord(ev[3 * j + 0], s);
         if (h->npA > 1) launch_dual_panels(s, h->panA.view, h->vecs, h->n, tab + j, st);
         else launch_dual(s, h->partA.view, h->A, h->vecs, tab + j, st);
-        if (ev) (void)hipEventRecord(ev[3 * j + 1], s);
+        if (timed) (void)hipEventRecord(ev[3 * j + 1], s);
         if (h->npP > 1) launch_primal_panels(s, h->panP.view, h->vecs, md, h->n, tab + j, st);
         else launch_primal(s, h->partP.view, h->P, h->vecs, md, tab + j, st, h->n);
-        if (ev) (void)hipEventRecord(ev[3 * j + 2], s);
+        if (timed) (void)hipEventRecord(ev[3 * j + 2], s);
         md ^= 1;
     }
     int32_t sa, sp;
@@ -874,7 +877,7 @@ int get_graph(qp_handle *h, const DevSettings &ds, int md_in, hipGraphExec_t *ou
     if (!h->graph[md_in]) {
         hipGraph_t g;
         HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_interval(h, ds, md_in, ds.interval, nullptr);
+        enqueue_interval(h, ds, md_in, ds.interval, nullptr, 1);
         HIPCHK(hipStreamEndCapture(h->stream, &g));
         hipError_t e = hipGraphInstantiate(&h->graph[md_in], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -1071,6 +1074,7 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
     DevSettings ds = dev_settings(h);
     const int L = ds.interval;
     const bool profile = h->set.profile != 0;
+    const int stride = profile ? h->set.profile : 1;  // time every stride-th iteration
     const bool use_graph = h->set.use_graph != 0 && !profile;
     State *st = h->state.as<State>();
     h->log.clear();
@@ -1154,15 +1158,16 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
         // an interval enqueued after the solve ended ran as no-ops: not timed
         if (profile && !last.done) {
             const hipEvent_t *ev = h->prof_ev.data() + (size_t)f.evset * 3 * L;
-            for (int j = 0; j < len; ++j) {
+            int timed = 0;
+            for (int j = 0; j < len; j += stride, ++timed) {
                 float a = 0.f, b = 0.f;
                 HIPCHK(hipEventElapsedTime(&a, ev[3 * j + 0], ev[3 * j + 1]));
                 HIPCHK(hipEventElapsedTime(&b, ev[3 * j + 1], ev[3 * j + 2]));
                 h->prof.dual_ms += a;
                 h->prof.primal_ms += b;
             }
-            if (m > 0) h->prof.dual_launches += len;
-            h->prof.primal_launches += len;
+            if (m > 0) h->prof.dual_launches += timed;
+            h->prof.primal_launches += timed;
         }
         if (S.checks > seen_checks) {
             seen_checks = S.checks;
@@ -1192,7 +1197,8 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
             HIPCHK(hipGraphLaunch(g, s));
         } else {
             enqueue_interval(h, ds, md, len,
-                             profile ? h->prof_ev.data() + (size_t)evset * 3 * L : nullptr);
+                             profile ? h->prof_ev.data() + (size_t)evset * 3 * L : nullptr,
+                             stride);
         }
         md = (md + len) & 1;
         enqueued += len;

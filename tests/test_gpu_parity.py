@@ -435,20 +435,24 @@ def test_rows_without_entries(orc, qpa):
     _assert_parity(orc, qp, o, g)
 
 
-def test_profile_mode_matches_graph_mode(orc, qpa):
-    """Profiling (direct launches, an event pair per phase, two event sets so one
-    interval stays in flight) computes exactly what graph replay does, and times
-    every phase of every iteration that ran."""
+@pytest.mark.parametrize("every", [1, 4])
+def test_profile_mode_matches_graph_mode(orc, qpa, every):
+    """Profiling (direct launches, events around the phases of every k-th iteration,
+    two event sets so one interval stays in flight) computes exactly what graph
+    replay does, and times the phases of every k-th iteration that ran."""
     qp = qpgen.large_random_qp(seed=2, n=30000, m=15000)
     out = {}
-    for prof in (0, 1):
+    for prof in (0, every):
         with qpa.Solver(qp, qpa.Settings(eps=1e-6, max_iter=1000, profile=prof)) as s:
             out[prof] = s.solve()
             if prof:
                 p = s.profile()
-    (x0, y0, r0), (x1, y1, r1) = out[0], out[1]
+    (x0, y0, r0), (x1, y1, r1) = out[0], out[every]
     assert r1["iterations"] == r0["iterations"] and r1["status"] == r0["status"]
     np.testing.assert_array_equal(x1, x0)
     np.testing.assert_array_equal(y1, y0)
-    assert p["dual_launches"] == r1["iterations"] and p["primal_launches"] == r1["iterations"]
+    # within each check interval of 64, iterations 0, k, 2k, ... are timed
+    full, rest = divmod(r1["iterations"], 64)
+    timed = full * len(range(0, 64, every)) + len(range(0, rest, every))
+    assert p["dual_launches"] == timed and p["primal_launches"] == timed
     assert p["dual_ms"] > 0.0 and p["primal_ms"] > 0.0
