@@ -1041,6 +1041,7 @@ static int upload_sliced(const HostSliced &h, const double *csr_val, hipStream_t
         (rc = col.upload(h.col.data(), h.col.size() * 4)) ||
         (rc = src.upload(h.src.data(), h.src.size() * 8)) || (rc = val.alloc((size_t)len * 8 + 16)))
         return rc;
+    (void)hipGetLastError();  // launch errors are read below: drop any earlier one
     if (len > 0)
         hipLaunchKernelGGL(k_sliced_gather, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s,
                            val.as<double>(), csr_val, src.as<int64_t>(), len);
@@ -1644,6 +1645,7 @@ static int run_batch(BatchData *bd, const qp_settings *s, int ms, const qp_warm_
                            ? (int64_t)(s->time_limit_s * 1000.0 * (double)bd->wall_khz)
                            : 0;
     DevSettings ds = batch_settings(s);
+    (void)hipGetLastError();  // launch errors are read below: drop any earlier one
     int rc = run_classes(bd, [&](int k, hipStream_t cs) {
         int lo = bd->order_off[k], hi = bd->order_off[k + 1];
         if (max_count && max_count[k] >= 0 && hi - lo > max_count[k]) hi = lo + max_count[k];

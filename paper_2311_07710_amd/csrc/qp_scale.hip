@@ -137,6 +137,7 @@ int precondition_device(hipStream_t s, const ScaleInput &in, double *work, doubl
     v.st = work;
     v.f = work + R;
     v.d = d;
+    (void)hipGetLastError();  // launch errors are read below: drop any earlier one
     hipLaunchKernelGGL(k_fill_one, dim3(grid_of(R)), dim3(256), 0, s, d, R);
     const unsigned rows_grid = (unsigned)((R + WAVES - 1) / WAVES);
     auto step = [&](int kind) {
