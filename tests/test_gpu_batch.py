@@ -258,3 +258,20 @@ def test_batch_sliced_layout_edges(orc, qpa):
         xg, yg, rg = bs.solve()
         bs.close()
         _compare(batch, xg, yg, rg, ref)
+
+
+def test_batch_instance_too_large_for_lds(orc, qpa):
+    """An instance whose vectors cannot live in LDS (3 n + m = 24500 doubles) runs
+    with all vectors in HBM next to instances that keep them in LDS."""
+    big = qpgen.eq_qp(seed=8, n=7000)
+    assert 3 * big.n + big.m > 160 * 1024 // 8
+    insts = [big, qpgen.tiny_random_qp(5), _mixed_batch()[2]]
+    batch = qpgen.concat_batch(insts)
+    ref = _oracle_all(orc, insts, eps=1e-6)
+    for threads in (256, 1024):
+        bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6))
+        bs.set_norms([r[3] for r in ref], [r[4] for r in ref])
+        bs.set_threads([threads] * 4)
+        xg, yg, rg = bs.solve()
+        bs.close()
+        _compare(batch, xg, yg, rg, ref)
