@@ -563,6 +563,21 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
         }
         __syncthreads();
         int sp = 0, md = 0;
+        // A thread's rows are the same in every iteration: the sliced position, width
+        // (0 for a long row) and length of its first row of each phase are read once
+        // here, so the common case (one row per thread and phase) starts every
+        // iteration with the matrix loads themselves.
+        int a_e = 0, a_w = 0, a_len = 0, p_e = 0, p_w = 0, p_len = 0;
+        if (t < m) {
+            a_len = arp[t + 1] - arp[t];
+            a_e = sa_start[t / SLICE] + t % SLICE;
+            a_w = a_len <= LONG_ROW ? sa_width[t / SLICE] : 0;
+        }
+        if (t < n) {
+            p_len = prp[t + 1] - prp[t];
+            p_e = sp_start[t / SLICE] + t % SLICE;
+            p_w = p_len <= LONG_ROW ? sp_width[t / SLICE] : 0;
+        }
         while (!S.done) {
             const int64_t left = ds.max_iter - S.total;
             const int len = (int)(left < ds.interval ? left : ds.interval);
@@ -580,17 +595,22 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
                 // dual phase: y+ = proj_Y(y - d (A x~ - b)), y-bar averaging
                 for (int i = t; i < m; i += NT) {
                     // Every load the row needs is issued before any result is used:
-                    // the slice's start and width (the slice is the wavefront's, so
-                    // these are scalar loads), the row pointers and the epilogue's
-                    // operands.  The row's results are computed unconditionally and only
-                    // the stores depend on the row being short (long rows: team loop).
-                    const int sl = __builtin_amdgcn_readfirstlane(i / SLICE);
-                    const int e = sa_start[sl] + i % SLICE, w = sa_width[sl];
-                    const int len = arp[i + 1] - arp[i];
+                    // the slice's start and width (the slice is the wavefront's), the
+                    // row pointers and the epilogue's operands; for the first row they
+                    // were read before the loop.  The row's results are computed
+                    // unconditionally and only the stores depend on the row being short
+                    // (long rows: team loop).
+                    int e = a_e, w = a_w, len = a_len;
+                    if (i != t) {
+                        const int sl = __builtin_amdgcn_readfirstlane(i / SLICE);
+                        len = arp[i + 1] - arp[i];
+                        e = sa_start[sl] + i % SLICE;
+                        w = len <= LONG_ROW ? sa_width[sl] : 0;
+                    }
                     const double bi = b[i];
                     const uint8_t ti = rt[i];
                     const bool mine = len <= LONG_ROW;
-                    const double s = sliced_dot(a.sa_col, a.sa_val, e, mine ? w : 0, len,
+                    const double s = sliced_dot(a.sa_col, a.sa_val, e, w, len,
                                                 [&](int cc) { return xt[cc]; });
                     double yn = y[i] - st.d * (s - bi);
                     if (ti == 1 && yn < 0.0) yn = 0.0;
@@ -619,13 +639,17 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
                 double *xout = md ? xmd0 : xmd1;
                 for (int jj = t; jj < n; jj += NT) {
                     // loads first, stores predicated (as in the dual phase)
-                    const int sl = __builtin_amdgcn_readfirstlane(jj / SLICE);
-                    const int e = sp_start[sl] + jj % SLICE, w = sp_width[sl];
-                    const int len = prp[jj + 1] - prp[jj];
+                    int e = p_e, w = p_w, len = p_len;
+                    if (jj != t) {
+                        const int sl = __builtin_amdgcn_readfirstlane(jj / SLICE);
+                        len = prp[jj + 1] - prp[jj];
+                        e = sp_start[sl] + jj % SLICE;
+                        w = len <= LONG_ROW ? sp_width[sl] : 0;
+                    }
                     const double cj = c[jj], lj = l[jj], uj = u[jj];
                     const bool mine = len <= LONG_ROW;
                     const double s = sliced_dot(
-                        a.sp_col, a.sp_val, e, mine ? w : 0, len,
+                        a.sp_col, a.sp_val, e, w, len,
                         [&](int cc) { return *(cc < n ? xin + cc : y + (cc - n)); });
                     const double xo = x[jj];
                     double xn, xb;
