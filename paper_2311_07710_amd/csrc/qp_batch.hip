@@ -568,15 +568,22 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
         // here, so the common case (one row per thread and phase) starts every
         // iteration with the matrix loads themselves.
         int a_e = 0, a_w = 0, a_len = 0, p_e = 0, p_w = 0, p_len = 0;
+        double a_b = 0.0, p_c = 0.0, p_l = 0.0, p_u = 0.0;
+        uint8_t a_rt = 0;
         if (t < m) {
             a_len = arp[t + 1] - arp[t];
             a_e = sa_start[t / SLICE] + t % SLICE;
             a_w = a_len <= LONG_ROW ? sa_width[t / SLICE] : 0;
+            a_b = b[t];
+            a_rt = rt[t];
         }
         if (t < n) {
             p_len = prp[t + 1] - prp[t];
             p_e = sp_start[t / SLICE] + t % SLICE;
             p_w = p_len <= LONG_ROW ? sp_width[t / SLICE] : 0;
+            p_c = c[t];
+            p_l = l[t];
+            p_u = u[t];
         }
         while (!S.done) {
             const int64_t left = ds.max_iter - S.total;
@@ -601,14 +608,16 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
                     // unconditionally and only the stores depend on the row being short
                     // (long rows: team loop).
                     int e = a_e, w = a_w, len = a_len;
+                    double bi = a_b;
+                    uint8_t ti = a_rt;
                     if (i != t) {
                         const int sl = __builtin_amdgcn_readfirstlane(i / SLICE);
                         len = arp[i + 1] - arp[i];
                         e = sa_start[sl] + i % SLICE;
                         w = len <= LONG_ROW ? sa_width[sl] : 0;
+                        bi = b[i];
+                        ti = rt[i];
                     }
-                    const double bi = b[i];
-                    const uint8_t ti = rt[i];
                     const bool mine = len <= LONG_ROW;
                     const double s = sliced_dot(a.sa_col, a.sa_val, e, w, len,
                                                 [&](int cc) { return xt[cc]; });
@@ -640,13 +649,16 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
                 for (int jj = t; jj < n; jj += NT) {
                     // loads first, stores predicated (as in the dual phase)
                     int e = p_e, w = p_w, len = p_len;
+                    double cj = p_c, lj = p_l, uj = p_u;
                     if (jj != t) {
                         const int sl = __builtin_amdgcn_readfirstlane(jj / SLICE);
                         len = prp[jj + 1] - prp[jj];
                         e = sp_start[sl] + jj % SLICE;
                         w = len <= LONG_ROW ? sp_width[sl] : 0;
+                        cj = c[jj];
+                        lj = l[jj];
+                        uj = u[jj];
                     }
-                    const double cj = c[jj], lj = l[jj], uj = u[jj];
                     const bool mine = len <= LONG_ROW;
                     const double s = sliced_dot(
                         a.sp_col, a.sp_val, e, w, len,
