@@ -414,13 +414,14 @@ def bench_warmstart(log, count):
     omega = np.array([r["omega"] for r in res])
     log(f"[bench] {ntr} label solves (1e-8) in {t_lab:.1f}s")
     t = time.perf_counter()
+    epochs = 60
     model = ws.train(ws.features(fam, tr), ws.targets(X, Y, omega), fam.base.n, fam.base.m,
-                     hidden=(512, 512), epochs=30, batch=256, lr=3e-4, seed=0,
+                     hidden=(512, 512), epochs=epochs, batch=256, lr=3e-4, seed=0,
                      log=lambda msg: log(f"[bench] train: {msg}"))
     train_s = time.perf_counter() - t
     # GEMM work of training: forward 2*in*out per layer and sample, backward twice that
     sizes = model.mlp.sizes
-    steps = 30 * (ntr // 256)
+    steps = epochs * (ntr // 256)
     gemm_flops = 3.0 * 2.0 * sum(a * b for a, b in zip(sizes[:-1], sizes[1:])) * 256 * steps
     log(f"[bench] MLP trained in {train_s:.1f}s ({gemm_flops / train_s / 1e12:.2f} TFLOP/s of "
         f"BF16 GEMM work incl. host loop), loss {model.history[0]:.4f} -> "
