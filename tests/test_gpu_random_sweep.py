@@ -103,3 +103,60 @@ def test_random_sweep_single_and_batch(orc, qpa):
         v0, v1 = batch.var_off[j], batch.var_off[j + 1]
         r0, r1 = batch.row_off[j], batch.row_off[j + 1]
         _close(rb[j], xb[v0:v1], yb[r0:r1], refs[i])
+
+
+def _oracle_pre(orc, qp, eps, max_iter):
+    sc, dv, dr = orc.precondition(qp)
+    nA, _ = orc.norm_A(sc, 1000, 1e-7)
+    nQ, _ = orc.norm_Q(sc, 1000, 1e-7)
+    s = orc.OracleSettings(eps=eps, max_iter=max_iter, norm_A=nA, norm_Q=nQ)
+    x, y, r, _ = orc.solve_scaled(sc, qp, dv, dr, s)
+    return x, y, r, nA, nQ
+
+
+def test_random_sweep_preconditioned(orc, qpa):
+    """The same sweep with the Sec. 5 preprocessing on (device scaling, single and
+    batched, against the oracle's own scaling)."""
+    eps, max_iter = 1e-6, 6000
+    insts = [_instance(s) for s in SEEDS]
+    refs = [_oracle_pre(orc, qp, eps, max_iter) for qp in insts]
+    keep = [i for i, r in enumerate(refs) if r[3] > 0.0 or r[4] > 0.0]
+    for i in keep:
+        qp, ref = insts[i], refs[i]
+        with qpa.Solver(qp, qpa.Settings(eps=eps, max_iter=max_iter, norm_A=ref[3],
+                                         norm_Q=ref[4], precondition=1)) as s:
+            xg, yg, g = s.solve()
+        _close(g, xg, yg, ref)
+    batch = qpgen.concat_batch([insts[i] for i in keep])
+    with qpa.BatchSolver(batch, qpa.Settings(eps=eps, max_iter=max_iter,
+                                             precondition=1)) as bs:
+        bs.set_norms([refs[i][3] for i in keep], [refs[i][4] for i in keep])
+        xb, yb, rb = bs.solve()
+    for j, i in enumerate(keep):
+        v0, v1 = batch.var_off[j], batch.var_off[j + 1]
+        r0, r1 = batch.row_off[j], batch.row_off[j + 1]
+        _close(rb[j], xb[v0:v1], yb[r0:r1], refs[i])
+
+
+def test_random_sweep_plain_pdhg(orc, qpa):
+    """The sweep in the Sec. 5 PDHG baseline (no momentum, restarts off)."""
+    eps, max_iter = 1e-6, 3000
+    insts = [_instance(s) for s in SEEDS]
+    refs = []
+    for qp in insts:
+        nA, _ = orc.norm_A(qp, 1000, 1e-7)
+        nQ, _ = orc.norm_Q(qp, 1000, 1e-7)
+        s = orc.OracleSettings(eps=eps, max_iter=max_iter, norm_A=nA, norm_Q=nQ, momentum=0,
+                               restart_mode=orc.RESTART_NONE)
+        x, y, r, _ = orc.solve(qp, s)
+        refs.append((x, y, r, nA, nQ))
+    keep = [i for i, r in enumerate(refs) if r[3] > 0.0 or r[4] > 0.0]
+    batch = qpgen.concat_batch([insts[i] for i in keep])
+    with qpa.BatchSolver(batch, qpa.Settings(eps=eps, max_iter=max_iter, momentum=0,
+                                             restart_mode=3)) as bs:
+        bs.set_norms([refs[i][3] for i in keep], [refs[i][4] for i in keep])
+        xb, yb, rb = bs.solve()
+    for j, i in enumerate(keep):
+        v0, v1 = batch.var_off[j], batch.var_off[j + 1]
+        r0, r1 = batch.row_off[j], batch.row_off[j + 1]
+        _close(rb[j], xb[v0:v1], yb[r0:r1], refs[i])
