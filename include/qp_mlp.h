@@ -7,7 +7,7 @@
  * maps the varying data of a parametrised QP family to a starting point and a
  * primal weight; it is trained on solutions the solver itself produced.  The
  * solver's own KKT test (qp_solve / qp_batch_solve with warm_fallback = 1)
- * judges every prediction, and a cold start is used whenever the prediction is
+ * checks every prediction, and a cold start is used whenever the prediction is
  * worse.
  *
  * Network: sizes[0] -> sizes[1] -> ... -> sizes[L], ReLU after every hidden

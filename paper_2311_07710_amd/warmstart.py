@@ -6,7 +6,7 @@ primal point (x, y_factors), the duals of all rows and log(omega) of a cold
 rAPDHG solve; it is trained on solutions the batched solver produced.  A
 prediction is only a starting point: qp_batch_solve with warm_fallback = 1
 keeps it only if its relative KKT error beats the cold start's, and the
-solve's own termination test judges the result.
+solve's own termination test checks the result.
 
 Host code here only prepares arrays (standardisation) and drives the library;
 the solves, the forward/backward passes and the Adam steps run on the GPU.
