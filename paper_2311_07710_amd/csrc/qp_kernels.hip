@@ -94,31 +94,53 @@ __device__ double block_sum_value(double s, double *scratch) {
     return t;
 }
 
-// Chunk partial sums of a long row: thread 0 publishes its W partial sums;
-// the last chunk to arrive (atomic counter) adds all partials in chunk order.
-// Returns true in thread 0 of the last block, with the row totals in tot[].
+// Chunk partial sums of a long row: thread 0 publishes the chunk's W partial sums;
+// the last chunk to arrive (atomic counter) adds all partials of the row.  The whole
+// last workgroup reads them in parallel (thread t adds partials t, t + BS, ... in
+// order, then a fixed reduction tree over the threads), so a row of many chunks costs
+// one memory round trip instead of one per chunk; the order is fixed, so the result
+// is deterministic.  Returns true in thread 0 of the last workgroup, with the row
+// totals in tot[].
+//
+// The chunks of a row run on different XCDs, whose L2s are not coherent with each
+// other.  The partials are therefore written and read with agent-scope atomic
+// accesses (write-through / cache-bypassing), and the writer waits for its stores to
+// be acknowledged before it bumps the counter.  No agent-scope fence is used: on this
+// GPU one writes back and invalidates the whole L2 of the XCD, which evicted the
+// gathered vector of every other workgroup there.
 template <int W>
-__device__ bool chunk_finish(const Blocks &bk, int bi, int lr, const double *part, double *tot) {
+__device__ bool finish_chunks(int32_t *count, const int32_t *first, const int32_t *nchunk,
+                              double *partial, int bi, int lr, const double *part, double *tot) {
     __shared__ int is_last;
+    __shared__ double scratch[BS / 64];
     if (threadIdx.x == 0) {
-        for (int v = 0; v < W; ++v) bk.lr_partial[(size_t)bi * 4 + v] = part[v];
-        __threadfence();
-        const int old = atomicAdd(&bk.lr_count[lr], 1);
-        is_last = (old == bk.lr_nchunk[lr] - 1);
+        for (int v = 0; v < W; ++v)
+            __hip_atomic_store(&partial[(size_t)bi * 4 + v], part[v], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // keeps the order in code
+        __builtin_amdgcn_s_waitcnt(0);  // the partial stores are acknowledged
+        const int old = atomicAdd(&count[lr], 1);
+        is_last = (old == nchunk[lr] - 1);
     }
     __syncthreads();
     if (!is_last) return false;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int f = bk.lr_first[lr], nc = bk.lr_nchunk[lr];
-        for (int v = 0; v < W; ++v) tot[v] = 0.0;
-        for (int ch = 0; ch < nc; ++ch)
-            for (int v = 0; v < W; ++v)
-                tot[v] = tot[v] + __hip_atomic_load(&bk.lr_partial[(size_t)(f + ch) * 4 + v],
-                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&bk.lr_count[lr], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    const int f = first[lr], nc = nchunk[lr];
+    double acc[W];
+    for (int v = 0; v < W; ++v) acc[v] = 0.0;
+    for (int ch = threadIdx.x; ch < nc; ch += BS)
+        for (int v = 0; v < W; ++v)
+            acc[v] = acc[v] + __hip_atomic_load(&partial[(size_t)(f + ch) * 4 + v],
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int v = 0; v < W; ++v) tot[v] = block_sum_value(acc[v], scratch);
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&count[lr], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return threadIdx.x == 0;
+}
+
+template <int W>
+__device__ bool chunk_finish(const Blocks &bk, int bi, int lr, const double *part, double *tot) {
+    return finish_chunks<W>(bk.lr_count, bk.lr_first, bk.lr_nchunk, bk.lr_partial, bi, lr, part,
+                            tot);
 }
 
 // ---------------------------------------------------------------------------
@@ -1189,26 +1211,8 @@ namespace qpk {
 template <int W>
 __device__ bool panel_chunk_finish_w(const Panels &pn, int bi, int lr, const double *part,
                                      double *tot) {
-    __shared__ int is_last;
-    if (threadIdx.x == 0) {
-        for (int v = 0; v < W; ++v) pn.lr_partial[(size_t)bi * 4 + v] = part[v];
-        __threadfence();
-        const int old = atomicAdd(&pn.lr_count[lr], 1);
-        is_last = (old == pn.lr_nchunk[lr] - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int f = pn.lr_first[lr], nc = pn.lr_nchunk[lr];
-        for (int v = 0; v < W; ++v) tot[v] = 0.0;
-        for (int ch = 0; ch < nc; ++ch)
-            for (int v = 0; v < W; ++v)
-                tot[v] = tot[v] + __hip_atomic_load(&pn.lr_partial[(size_t)(f + ch) * 4 + v],
-                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&pn.lr_count[lr], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return threadIdx.x == 0;
+    return finish_chunks<W>(pn.lr_count, pn.lr_first, pn.lr_nchunk, pn.lr_partial, bi, lr, part,
+                            tot);
 }
 
 __device__ bool panel_chunk_finish(const Panels &pn, int bi, int lr, double part, double *tot) {

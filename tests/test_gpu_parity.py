@@ -456,3 +456,23 @@ def test_profile_mode_matches_graph_mode(orc, qpa, every):
     timed = full * len(range(0, 64, every)) + len(range(0, rest, every))
     assert p["dual_launches"] == timed and p["primal_launches"] == timed
     assert p["dual_ms"] > 0.0 and p["primal_ms"] > 0.0
+
+
+@pytest.mark.parametrize("panels", [(1, 1), (8, 8)])
+def test_long_row_chunks_repeatable(orc, qpa, panels):
+    """Rows split into chunks that finish on different XCDs (a 20000-entry budget row,
+    and with 8 panels every row of P spread over all XCDs): repeated solves give
+    bitwise the same iterates, and match the oracle."""
+    qp = qpgen.portfolio_qp(seed=3, n_assets=20000, k=40)
+    o, g = _pair(orc, qpa, qp, eps=1e-6, max_iter=3000, panels=panels)
+    _assert_parity(orc, qp, o, g)
+    nA, nQ = g[2]["norm_A"], g[2]["norm_Q"]
+    runs = []
+    with qpa.Solver(qp, qpa.Settings(eps=1e-6, max_iter=3000, norm_A=nA, norm_Q=nQ,
+                                     panels_dual=panels[0], panels_primal=panels[1])) as s:
+        for _ in range(3):
+            runs.append(s.solve())
+    for x, y, r in runs[1:]:
+        assert r["iterations"] == runs[0][2]["iterations"]
+        np.testing.assert_array_equal(x, runs[0][0])
+        np.testing.assert_array_equal(y, runs[0][1])
