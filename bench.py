@@ -332,8 +332,9 @@ def bench_ablation(log):
 
 def bench_classes(log):
     """The seven synthetic classes of the paper's large-scale set at medium size (about
-    1-4 M nonzeros each), preconditioned (Sec. 5), solved to relKKT 1e-6 one instance at
-    a time: iterations, seconds and iterations per second."""
+    1-4 M nonzeros each), plus the full-size factor-model portfolio QP (5e5 assets, 1000
+    factors), preconditioned (Sec. 5), solved to relKKT 1e-6 one instance at a time:
+    iterations, seconds and iterations per second."""
     import numpy as np
     import paper_2311_07710_amd as qpa
     import qpgen
@@ -343,6 +344,7 @@ def bench_classes(log):
         "control": lambda: qpgen.mpc_qp(np.random.default_rng(14), 2000, 20, 10,
                                         name="control_T2000_nx20_nu10"),
         "portfolio": lambda: qpgen.portfolio_qp(seed=15, n_assets=200_000, k=1000),
+        "portfolio_full_size": lambda: qpgen.portfolio_qp(),   # 5e5 assets, 1000 factors
         "huber": lambda: qpgen.huber_qp(seed=16, n_features=10_000, m_samples=100_000,
                                         density=0.003),
         "lasso": lambda: qpgen.lasso_qp(seed=17, n_features=10_000, m_samples=100_000,
