@@ -291,11 +291,12 @@ struct DevPanels {
 };
 
 // panel count: explicit setting, else 4 (two XCDs per panel) when the gathered
-// vector exceeds 2 MB, i.e. would not stay in one XCD's 4 MB L2 next to the
-// streamed matrix (4 measured fastest among 1/2/4/8 on the large random QP)
+// vector exceeds 6 MB. Measured: one panel ties or wins up to 4.8 MB (random and
+// equality QPs with n + m up to 6e5, where the gathers still mostly hit L2 and the
+// combine kernel is pure cost); 4 wins among 1/2/4/8 at 8-12 MB (n = 1e6)
 int choose_panels(int32_t setting, int64_t gathered_len) {
     if (setting == 1 || setting == 2 || setting == 4 || setting == 8) return setting;
-    return gathered_len * 8 > (2 << 20) ? 4 : 1;
+    return gathered_len * 8 > (6 << 20) ? 4 : 1;
 }
 
 // copies `count` elements of an input array (host or device) to a host vector
