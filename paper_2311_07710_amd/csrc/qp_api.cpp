@@ -923,6 +923,11 @@ int qp_create(const qp_problem_desc *d, const qp_settings *settings, qp_handle *
     if ((rc = check_settings(s))) return rc;
     if (d->n <= 0) return fail(QP_ERR_INVALID_ARGUMENT, "n must be positive");
     if (d->m < 0) return fail(QP_ERR_INVALID_ARGUMENT, "m must be >= 0");
+    // P = [Q | -A'] is indexed with int32: its columns run over (x, y) and its entries
+    // over the nonzeros of Q and A; checked before any array is read
+    if (d->n + d->m >= ((int64_t)1 << 31) ||
+        d->Q.nnz + (d->m > 0 ? d->A.nnz : 0) >= ((int64_t)1 << 31))
+        return fail(QP_ERR_INVALID_ARGUMENT, "problem exceeds int32 indexing");
     if (d->mem_space != QP_MEM_HOST && d->mem_space != QP_MEM_DEVICE)
         return fail(QP_ERR_INVALID_ARGUMENT, "unknown mem_space %d", d->mem_space);
     if (!d->Q.row_ptr || (d->Q.nnz > 0 && (!d->Q.col_idx || !d->Q.val)))

@@ -123,6 +123,21 @@ def test_bad_settings_rejected(kw, needle):
     assert rc == B.QP_ERR_INVALID_ARGUMENT and needle in msg
 
 
+@pytest.mark.parametrize("field,value", [("n", 2**31 - 10), ("Q.nnz", 2**31), ("A.nnz", 2**31 - 1)])
+def test_int32_index_range_rejected_before_reading(field, value):
+    """Sizes beyond int32 indexing of P = [Q | -A'] are refused from the descriptor's
+    sizes alone: the (small) arrays behind it are never read at those sizes."""
+    lib = qpa.load()
+    keep = _Keep(False)
+    d = _desc(_tiny(), keep, batch=False)
+    obj, _, attr = field.rpartition(".")
+    setattr(getattr(d, obj) if obj else d, attr, value)
+    h = C.c_void_p()
+    rc = lib.qp_create(C.byref(d), C.byref(Settings().c_struct()), C.byref(h))
+    assert rc == B.QP_ERR_INVALID_ARGUMENT
+    assert "exceeds int32" in lib.qp_last_error().decode()
+
+
 def test_null_arguments():
     lib = qpa.load()
     assert lib.qp_create(None, None, None) == B.QP_ERR_INVALID_ARGUMENT
