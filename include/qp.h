@@ -103,6 +103,23 @@ typedef struct {
                                 NULL; the library waits for it before reading them */
 } qp_problem_desc;
 
+/* One record per relKKT evaluation of a single-QP solve (settings.log_checks,
+ * settings.log_cb): the restart test of Sec. 6 at that evaluation. */
+typedef struct {
+    int64_t total;           /* iterations done at this evaluation */
+    int64_t k;               /* inner index after the evaluation (0 after a restart) */
+    double r_cur, r_avg;     /* relKKT of the iterate z and of the average z-bar */
+    int32_t candidate;       /* 0 = z, 1 = z-bar */
+    int32_t restarted;
+    double omega;            /* primal weight after the evaluation */
+} qp_check_info;
+
+/* Per-evaluation callback (settings.log_cb).  It runs on the host thread inside
+ * qp_solve, once per evaluation and in order, as the host reads that evaluation's
+ * state; the next check interval is enqueued only after it returns, so a slow
+ * callback slows the solve.  It must not call the library with the same handle. */
+typedef void (*qp_log_fn)(const qp_check_info *info, void *user);
+
 typedef struct {
     double eps;              /* relKKT tolerance; default 1e-6 */
     int64_t max_iter;        /* default 200000 (Sec. 5) */
@@ -161,6 +178,10 @@ typedef struct {
     int32_t check_symmetry;  /* 1: qp_create rejects a Q that differs from its transpose
                                 (pattern or value, per instance); PSD is never checked.
                                 Default 0 */
+    qp_log_fn log_cb;        /* NULL (default) or called once per evaluation of a single-QP
+                                solve with that evaluation's record (whether or not
+                                log_checks is set); not called for a batch handle */
+    void *log_user;          /* passed unchanged as log_cb's second argument */
 } qp_settings;
 
 typedef struct {
@@ -181,15 +202,6 @@ typedef struct {
     double norm_A, norm_Q;   /* operator norms used */
     double solve_time_s;     /* host wall time of the solve */
 } qp_result;
-
-typedef struct {
-    int64_t total;           /* iterations done at this evaluation */
-    int64_t k;               /* inner index after the evaluation (0 after a restart) */
-    double r_cur, r_avg;     /* relKKT of the iterate z and of the average z-bar */
-    int32_t candidate;       /* 0 = z, 1 = z-bar */
-    int32_t restarted;
-    double omega;            /* primal weight after the evaluation */
-} qp_check_info;
 
 typedef struct {
     int64_t dual_launches, primal_launches;  /* phases timed */
@@ -243,7 +255,7 @@ int qp_batch_set_threads(qp_handle *h, const int32_t *threads);
 /* Copies up to cap records of the last solve's evaluation log (settings.log_checks). */
 int qp_get_check_log(qp_handle *h, qp_check_info *buf, int64_t cap, int64_t *len);
 
-/* Kernel timings of the last solve run with settings.profile = 1. */
+/* Phase timings of the last solve run with settings.profile = k >= 1. */
 int qp_get_profile(qp_handle *h, qp_profile *out);
 
 /* Norms in use by the handle: one value each for a single QP, num_instances values

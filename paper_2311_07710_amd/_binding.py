@@ -39,6 +39,15 @@ class qp_problem_desc(C.Structure):
                 ("stream", _vp)]
 
 
+class qp_check_info(C.Structure):
+    _fields_ = [("total", C.c_int64), ("k", C.c_int64), ("r_cur", C.c_double),
+                ("r_avg", C.c_double), ("candidate", C.c_int32), ("restarted", C.c_int32),
+                ("omega", C.c_double)]
+
+
+qp_log_fn = C.CFUNCTYPE(None, C.POINTER(qp_check_info), C.c_void_p)
+
+
 class qp_settings(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_iter", C.c_int64), ("time_limit_s", C.c_double),
                 ("check_every", C.c_int32), ("restart_mode", C.c_int32), ("fixed_K", C.c_int32),
@@ -51,7 +60,7 @@ class qp_settings(C.Structure):
                 ("device", C.c_int32), ("panels_dual", C.c_int32), ("panels_primal", C.c_int32),
                 ("momentum", C.c_int32), ("precondition", C.c_int32), ("ruiz_iters", C.c_int32),
                 ("detect_infeasibility", C.c_int32), ("eps_infeasible", C.c_double),
-                ("check_symmetry", C.c_int32)]
+                ("check_symmetry", C.c_int32), ("log_cb", qp_log_fn), ("log_user", _vp)]
 
 
 class qp_warm_start(C.Structure):
@@ -64,12 +73,6 @@ class qp_result(C.Structure):
                 ("r_primal", C.c_double), ("r_dual", C.c_double), ("r_gap", C.c_double),
                 ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("omega", C.c_double),
                 ("norm_A", C.c_double), ("norm_Q", C.c_double), ("solve_time_s", C.c_double)]
-
-
-class qp_check_info(C.Structure):
-    _fields_ = [("total", C.c_int64), ("k", C.c_int64), ("r_cur", C.c_double),
-                ("r_avg", C.c_double), ("candidate", C.c_int32), ("restarted", C.c_int32),
-                ("omega", C.c_double)]
 
 
 class qp_profile(C.Structure):

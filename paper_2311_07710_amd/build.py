@@ -25,7 +25,7 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # per-source extra flags
 SOURCES = {
-    "qp_kernels.hip": ["-ffp-contract=off", "-munsafe-fp-atomics"],
+    "qp_kernels.hip": ["-ffp-contract=off"],
     "qp_batch.hip": ["-ffp-contract=off"],
     "qp_scale.hip": ["-ffp-contract=off"],
     "qp_api.cpp": ["-ffp-contract=off", "-x", "hip"],

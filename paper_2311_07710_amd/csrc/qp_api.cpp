@@ -422,6 +422,8 @@ void qp_default_settings(qp_settings *s) {
     s->detect_infeasibility = 0;
     s->eps_infeasible = 1e-8;
     s->check_symmetry = 0;
+    s->log_cb = nullptr;
+    s->log_user = nullptr;
 }
 
 const char *qp_last_error(void) { return qph::g_err.c_str(); }
@@ -1177,7 +1179,7 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
         }
         if (S.checks > seen_checks) {
             seen_checks = S.checks;
-            if (h->set.log_checks) {
+            if (h->set.log_checks || h->set.log_cb) {
                 qp_check_info ci;
                 ci.total = S.total;
                 ci.k = S.k;
@@ -1186,7 +1188,8 @@ int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_ou
                 ci.candidate = S.cand;
                 ci.restarted = S.restart_flag;
                 ci.omega = S.omega;
-                h->log.push_back(ci);
+                if (h->set.log_checks) h->log.push_back(ci);
+                if (h->set.log_cb) h->set.log_cb(&ci, h->set.log_user);
             }
         }
         last = S;

@@ -46,11 +46,21 @@ class Settings:
     detect_infeasibility: int = 0
     eps_infeasible: float = 1e-8
     check_symmetry: int = 0
+    # called with a dict per relKKT evaluation of a single-QP solve (see qp_log_fn)
+    log_cb: object = None
 
     def c_struct(self) -> B.qp_settings:
+        """The C settings; a log_cb is wrapped in a C function pointer that the returned
+        struct keeps alive (hold the struct as long as the handle)."""
         s = B.qp_settings()
         for f in fields(self):
+            if f.name == "log_cb":
+                continue
             setattr(s, f.name, getattr(self, f.name))
+        if self.log_cb is not None:
+            fn = self.log_cb
+            s.log_cb = B.qp_log_fn(lambda p, _u: fn(
+                {name: getattr(p.contents, name) for name, _ in B.qp_check_info._fields_}))
         return s
 
 
@@ -127,7 +137,8 @@ class Solver:
         keep = _Keep(device_arrays)
         desc = _desc(qp, keep, batch=False)
         h = C.c_void_p()
-        B.check(self.lib.qp_create(C.byref(desc), C.byref(self.settings.c_struct()), C.byref(h)))
+        self._cs = self.settings.c_struct()  # keeps a log_cb thunk alive with the handle
+        B.check(self.lib.qp_create(C.byref(desc), C.byref(self._cs), C.byref(h)))
         self.h = h
 
     def close(self):
@@ -210,7 +221,8 @@ class BatchSolver:
         keep = _Keep(device_arrays)
         desc = _desc(batch, keep, batch=True)
         h = C.c_void_p()
-        B.check(self.lib.qp_create(C.byref(desc), C.byref(self.settings.c_struct()), C.byref(h)))
+        self._cs = self.settings.c_struct()  # keeps a log_cb thunk alive with the handle
+        B.check(self.lib.qp_create(C.byref(desc), C.byref(self._cs), C.byref(h)))
         self.h = h
 
     def close(self):

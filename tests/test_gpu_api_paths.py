@@ -74,3 +74,39 @@ def test_time_limit(qpa):
     st = np.array([q["status"] for q in rb])
     assert (st == qpa.QP_TIME_LIMIT).any() and np.isin(st, [qpa.QP_OPTIMAL, qpa.QP_TIME_LIMIT]).all()
     assert np.all(np.isfinite(xb)) and np.all(np.isfinite(yb))
+
+
+def test_log_callback(orc, qpa):
+    """settings.log_cb sees every relKKT evaluation of a single solve, in order, with the
+    records qp_get_check_log keeps and the oracle's restart decisions; a batch handle
+    never calls it."""
+    qp = qpgen.tiny_random_qp(3)
+    nA, _ = orc.norm_A(qp, 1000, 1e-7)
+    nQ, _ = orc.norm_Q(qp, 1000, 1e-7)
+    _, _, ro, lo = orc.solve(qp, orc.OracleSettings(eps=1e-6, norm_A=nA, norm_Q=nQ),
+                             log_cap=100000)
+    seen = []
+    with qpa.Solver(qp, qpa.Settings(eps=1e-6, norm_A=nA, norm_Q=nQ, log_checks=1,
+                                     log_cb=seen.append)) as s:
+        _, _, r = s.solve()
+        kept = s.check_log()
+        assert r["iterations"] == ro["iterations"] and r["restarts"] == ro["restarts"]
+        assert seen == kept and len(seen) == len(lo) > 1
+        for a, b in zip(seen, lo):
+            assert (a["total"], a["k"], a["candidate"], a["restarted"]) == \
+                (b["total"], b["k"], b["candidate"], b["restarted"])
+        assert sum(c["restarted"] for c in seen) == r["restarts"]
+        # a second solve calls it again from the start; without log_checks as well
+        seen.clear()
+        s.solve()
+        assert seen == kept
+    seen2 = []
+    with qpa.Solver(qp, qpa.Settings(eps=1e-6, norm_A=nA, norm_Q=nQ,
+                                     log_cb=seen2.append)) as s:
+        s.solve()
+        assert s.check_log() == [] and seen2 == kept
+    calls = []
+    batch = qpgen.concat_batch([qpgen.tiny_random_qp(k) for k in (1, 2)])
+    with qpa.BatchSolver(batch, qpa.Settings(eps=1e-6, log_cb=calls.append)) as bs:
+        _, _, rb = bs.solve()
+    assert all(q["status"] == qpa.QP_OPTIMAL for q in rb) and calls == []
