@@ -105,6 +105,20 @@ def main():
         torch.cuda.synchronize()
         log("[bench] calibration copy: 256 MiB read + 256 MiB written")
         del src, dst
+    # measured streaming bandwidth: a plain 1 GiB device-to-device copy (read + write)
+    src = torch.ones(128 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    copy_gbs = 0.0
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        copy_gbs = max(copy_gbs, 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    log(f"[bench] device copy (1 GiB read + 1 GiB written): {copy_gbs:.0f} GB/s")
     t = time.time()
     qp = qpgen.large_random_qp()
     log(f"[bench] generated n={qp.n} m={qp.m} nnzA={qp.a_nnz} nnzQ={qp.q_nnz} "
@@ -143,6 +157,20 @@ def main():
     value = iters / elapsed
     ms_per_step = 1000.0 * elapsed / args.steps
 
+    # the same solves replayed as hipGraphs without phase timing: with the KKT evaluation
+    # every 64 iterations, and with one evaluation per step (the cost of the checks)
+    replay = {}
+    for ce in (64, args.iters):
+        with qpa.Solver(qp, qpa.Settings(eps=0.0, max_iter=args.iters, check_every=ce,
+                                         norm_A=nA, norm_Q=nQ)) as s4:
+            s4.solve()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            n_it = sum(s4.solve()[2]["iterations"] for _ in range(3))
+            torch.cuda.synchronize()
+            replay[f"check_every_{ce}"] = n_it / (time.perf_counter() - t)
+    log("[bench] graph replay: " + ", ".join(f"{k} {v:.0f} it/s" for k, v in replay.items()))
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -165,6 +193,7 @@ def main():
                       f"direct launches; both phases of every {profile}th iteration timed with hipEvents",
         },
         "create_s": create_s,
+        "iters_per_s_graph_replay": replay,
     }
     if profile and primal_n:
         d_avg = dual_ms / dual_n
@@ -176,7 +205,8 @@ def main():
                            "achieved": p_gbs,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": p_gbs / HBM_PEAK_GBS,
                            "traffic": measured_traffic(), "avg_us": 1000.0 * p_avg,
-                           "algorithmic_bytes_per_launch": primal_bytes}
+                           "algorithmic_bytes_per_launch": primal_bytes,
+                           "copy_GBps": copy_gbs, "frac_of_copy": p_gbs / copy_gbs}
         out["kernels"] = {
             "k_dual": {"avg_us": 1000.0 * d_avg, "bytes": dual_bytes, "GB/s": d_gbs,
                        "frac": d_gbs / HBM_PEAK_GBS, "launches": dual_n},
