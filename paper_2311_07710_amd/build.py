@@ -28,7 +28,7 @@ SOURCES = {
     "qp_kernels.hip": ["-ffp-contract=off"],
     "qp_batch.hip": ["-ffp-contract=off"],
     "qp_scale.hip": ["-ffp-contract=off"],
-    "qp_api.cpp": ["-ffp-contract=off", "-x", "hip"],
+    "qp_api.cpp": ["-ffp-contract=off", "-pthread", "-x", "hip"],
 }
 OPTIONAL = {
     "mlp_kernels.hip": [],
@@ -61,7 +61,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         objs = list(ex.map(lambda kv: _compile(kv[0], kv[1], verbose), jobs.items()))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

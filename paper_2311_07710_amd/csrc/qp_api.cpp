@@ -21,6 +21,7 @@
 #include <cstring>
 #include <deque>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/qp.h"
@@ -137,6 +138,23 @@ struct DevPartition {
     }
 };
 
+// Runs f(r0, r1) over [0, R) split into contiguous ranges on up to 16 host threads
+// (the caller's thread takes the first range).  Every row belongs to exactly one
+// range, so loops that write only their own rows' slots give the serial result.
+template <class F>
+void parallel_rows(int64_t R, F f) {
+    const int64_t hc = (int64_t)std::max(1u, std::thread::hardware_concurrency());
+    const int64_t T = std::min<int64_t>({hc, 16, std::max<int64_t>(1, R / 65536)});
+    if (T <= 1) {
+        f((int64_t)0, R);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int64_t t = 1; t < T; ++t) th.emplace_back(f, R * t / T, R * (t + 1) / T);
+    f((int64_t)0, R / T);
+    for (auto &x : th) x.join();
+}
+
 struct HostPanels {
     int np = 1;
     std::vector<PBlock> blk;
@@ -171,8 +189,11 @@ HostPanels build_panels(const int32_t *rowptr, const int32_t *col, const double 
     std::vector<int64_t> base(np + 1, 0);
     {
         std::vector<int64_t> cnt((size_t)np * R, 0);
-        for (int64_t r = 0; r < R; ++r)
-            for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) cnt[(size_t)pcol[col[e]] * R + r]++;
+        parallel_rows(R, [&](int64_t r0, int64_t r1) {
+            for (int64_t r = r0; r < r1; ++r)
+                for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e)
+                    cnt[(size_t)pcol[col[e]] * R + r]++;
+        });
         int64_t pos = 0;
         for (int k = 0; k < np; ++k) {
             base[k] = pos;
@@ -190,13 +211,15 @@ HostPanels build_panels(const int32_t *rowptr, const int32_t *col, const double 
         std::vector<int64_t> next((size_t)np * R);
         for (int k = 0; k < np; ++k)
             for (int64_t r = 0; r < R; ++r) next[(size_t)k * R + r] = hp.rowptr[(size_t)k * (R + 1) + r];
-        for (int64_t r = 0; r < R; ++r)
-            for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-                const int k = pcol[col[e]];
-                const int64_t q = next[(size_t)k * R + r]++;
-                hp.col[q] = col[e];
-                hp.val[q] = val[e];
-            }
+        parallel_rows(R, [&](int64_t r0, int64_t r1) {
+            for (int64_t r = r0; r < r1; ++r)
+                for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+                    const int k = pcol[col[e]];
+                    const int64_t q = next[(size_t)k * R + r]++;
+                    hp.col[q] = col[e];
+                    hp.val[q] = val[e];
+                }
+        });
     }
     // row blocks of each panel
     std::vector<std::vector<int32_t>> per_panel(np);
@@ -739,13 +762,16 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
     if ((rc = h->partA.upload(hpA)) || (rc = h->partP.upload(hpP))) return rc;
     h->npA = m > 0 ? choose_panels(h->set.panels_dual, n) : 1;
     h->npP = choose_panels(h->set.panels_primal, n + m);
-    if (h->npA > 1) {
-        HostPanels pa = build_panels(ar.data(), ac.data(), avp, m, n, h->npA);
-        if ((rc = h->panA.upload(pa, m))) return rc;
-    }
-    if (h->npP > 1) {
-        HostPanels pp = build_panels(pr.data(), pc.data(), pvp, n, n + m, h->npP);
-        if ((rc = h->panP.upload(pp, n))) return rc;
+    {
+        // the two panel layouts are independent: A's is built on a second thread
+        HostPanels pa, pp;
+        std::thread ta;
+        if (h->npA > 1)
+            ta = std::thread([&] { pa = build_panels(ar.data(), ac.data(), avp, m, n, h->npA); });
+        if (h->npP > 1) pp = build_panels(pr.data(), pc.data(), pvp, n, n + m, h->npP);
+        if (ta.joinable()) ta.join();
+        if (h->npA > 1 && (rc = h->panA.upload(pa, m))) return rc;
+        if (h->npP > 1 && (rc = h->panP.upload(pp, n))) return rc;
     }
 
     // solver vectors
