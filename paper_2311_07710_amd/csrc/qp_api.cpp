@@ -664,6 +664,48 @@ int gather_single(const qp_problem_desc *d, HostProblem &hp, const qp_settings &
     return QP_OK;
 }
 
+// P = [Q | -A']: row j holds Q's row j followed by the entries of column j of A, negated,
+// in increasing row index of A, with column index n + i.
+void build_p(int64_t n, int64_t m, int64_t annz, const int32_t *qr, const int32_t *qc,
+             const double *qv, const int32_t *ar, const int32_t *ac, const double *av,
+             std::vector<int32_t> &pr, std::vector<int32_t> &pc, std::vector<double> &pv) {
+    // Each host thread owns a range of P's rows (A's columns) and scans all of A in row
+    // order, so every row gets its entries in the serial order.
+    const int64_t pnnz = (int64_t)qr[n] + annz;
+    pr.assign(n + 1, 0);
+    pc.resize((size_t)pnnz);
+    pv.resize((size_t)pnnz);
+    std::vector<int64_t> acount(n, 0);
+    parallel_rows(n, [&](int64_t j0, int64_t j1) {
+        for (int64_t e = 0; e < annz; ++e) {
+            const int64_t j = ac[e];
+            if (j >= j0 && j < j1) acount[j]++;
+        }
+    });
+    for (int64_t j = 0; j < n; ++j) pr[j + 1] = (int32_t)(pr[j] + (qr[j + 1] - qr[j]) + acount[j]);
+    std::vector<int64_t> next(n);
+    parallel_rows(n, [&](int64_t j0, int64_t j1) {
+        for (int64_t j = j0; j < j1; ++j) {
+            int64_t pos = pr[j];
+            for (int64_t e = qr[j]; e < qr[j + 1]; ++e, ++pos) {
+                pc[pos] = qc[e];
+                pv[pos] = qv[e];
+            }
+            next[j] = pos;
+        }
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t e = ar[i]; e < ar[i + 1]; ++e) {
+                const int64_t j = ac[e];
+                if (j < j0 || j >= j1) continue;
+                const int64_t pos = next[j]++;
+                pc[pos] = (int32_t)(n + i);
+                pv[pos] = -av[e];
+            }
+    });
+}
+
+int64_t annz_of(const qp_problem_desc *d) { return d->m > 0 ? d->A.nnz : 0; }
+
 int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
     const int64_t n = d->n, m = d->m;
     const auto &qr = hp.qr, &qc = hp.qc, &ar = hp.ar, &ac = hp.ac;
@@ -672,27 +714,10 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
     int rc;
     const int64_t pnnz = d->Q.nnz + (m > 0 ? d->A.nnz : 0);
 
-    // P = [Q | -A'] ; the A' entries of row j follow the Q entries, ordered by A's row index
-    std::vector<int32_t> pr(n + 1, 0), pc((size_t)pnnz);
-    std::vector<double> pv((size_t)pnnz);
-    std::vector<int64_t> acount(n, 0);
-    for (int64_t e = 0; e < (m > 0 ? d->A.nnz : 0); ++e) acount[ac[e]]++;
-    for (int64_t j = 0; j < n; ++j) pr[j + 1] = (int32_t)(pr[j] + (qr[j + 1] - qr[j]) + acount[j]);
-    std::vector<int64_t> next(n);
-    for (int64_t j = 0; j < n; ++j) {
-        int64_t pos = pr[j];
-        for (int64_t e = qr[j]; e < qr[j + 1]; ++e, ++pos) {
-            pc[pos] = qc[e];
-            pv[pos] = qv[e];
-        }
-        next[j] = pos;
-    }
-    for (int64_t i = 0; i < m; ++i)
-        for (int64_t e = ar[i]; e < ar[i + 1]; ++e) {
-            const int64_t pos = next[ac[e]]++;
-            pc[pos] = (int32_t)(n + i);
-            pv[pos] = -av[e];
-        }
+    std::vector<int32_t> pr, pc;
+    std::vector<double> pv;
+    build_p(n, m, annz_of(d), qr.data(), qc.data(), qv.data(), ar.data(), ac.data(), av.data(),
+            pr, pc, pv);
 
     auto up = [&](DevMem &dm, const void *src, size_t bytes) -> int { return dm.upload(src, bytes); };
     if ((rc = up(h->a_rowptr, ar.data(), ar.size() * 4)) || (rc = up(h->a_col, ac.data(), ac.size() * 4)) ||
