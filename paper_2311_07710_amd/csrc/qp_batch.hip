@@ -1148,8 +1148,11 @@ static int run_classes(BatchData *bd, F launch) {
         HIPCHK(hipStreamWaitEvent(bd->cls_stream[k], bd->ev_fork, 0));
         launch(k, bd->cls_stream[k]);
         HIPCHK(hipEventRecord(bd->ev_join[k], bd->cls_stream[k]));
-        HIPCHK(hipStreamWaitEvent(bd->stream, bd->ev_join[k], 0));
     }
+    // The handle's stream waits for the classes only after every class is launched: with
+    // more streams than hardware queues a class stream may share a queue with it, and a
+    // wait queued there earlier would hold that class back until the previous one ends.
+    for (int k = NCLASS - 1; k >= 0; --k) HIPCHK(hipStreamWaitEvent(bd->stream, bd->ev_join[k], 0));
     return QP_OK;
 }
 
@@ -1291,9 +1294,29 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
     BatchData *bd = new BatchData();
     bd->B = B;
     bd->stream = stream;
+    // The size classes run concurrently on streams of their own.  Ordinary streams share
+    // the process's few hardware queues (4 by default), and two classes whose streams
+    // land on one queue run one after the other (measured: 4096 MPC QPs in 0.73 s against
+    // 0.50 s with a queue each).  A stream with a CU mask gets a hardware queue of its
+    // own; the mask enables every CU, so nothing else changes.
+    int ncu = 0, cdev = 0;
+    (void)hipGetDevice(&cdev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, cdev) != hipSuccess ||
+        ncu < 1)
+        ncu = 256;
+    std::vector<uint32_t> cu_mask((size_t)(ncu + 31) / 32, 0u);
+    for (int c = 0; c < ncu; ++c) cu_mask[(size_t)c / 32] |= 1u << (c % 32);
     for (int k = 0; k < NCLASS; ++k) {
-        if (hipStreamCreateWithFlags(&bd->cls_stream[k], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&bd->ev_join[k], hipEventDisableTiming) != hipSuccess) {
+        if (hipExtStreamCreateWithCUMask(&bd->cls_stream[k], (uint32_t)cu_mask.size(),
+                                         cu_mask.data()) != hipSuccess) {
+            (void)hipGetLastError();
+            bd->cls_stream[k] = nullptr;
+            if (hipStreamCreateWithFlags(&bd->cls_stream[k], hipStreamNonBlocking) != hipSuccess) {
+                delete bd;
+                return fail(QP_ERR_DEVICE, "batch: stream creation failed");
+            }
+        }
+        if (hipEventCreateWithFlags(&bd->ev_join[k], hipEventDisableTiming) != hipSuccess) {
             delete bd;
             return fail(QP_ERR_DEVICE, "batch: stream or event creation failed");
         }
