@@ -325,11 +325,14 @@ int choose_panels(int32_t setting, int64_t gathered_len) {
 // copies `count` elements of an input array (host or device) to a host vector
 template <class T>
 int fetch(std::vector<T> &dst, const T *src, int64_t count, int mem_space) {
-    dst.resize((size_t)count);
-    if (count == 0) return QP_OK;
+    if (count == 0) {
+        dst.clear();
+        return QP_OK;
+    }
     if (mem_space == QP_MEM_HOST) {
-        std::memcpy(dst.data(), src, (size_t)count * sizeof(T));
+        dst.assign(src, src + count);  // one pass, no zero fill before the copy
     } else {
+        dst.resize((size_t)count);
         HIPCHK(hipMemcpy(dst.data(), src, (size_t)count * sizeof(T), hipMemcpyDeviceToHost));
     }
     return QP_OK;

@@ -1178,11 +1178,17 @@ static DevSettings batch_settings(const qp_settings *s) {
 
 template <class T>
 static int fetch_vec(std::vector<T> &dst, const T *src, int64_t count, int ms) {
-    dst.resize((size_t)count);
-    if (count == 0) return QP_OK;
+    if (count == 0) {
+        dst.clear();
+        return QP_OK;
+    }
     if (!src) return fail(QP_ERR_INVALID_ARGUMENT, "missing batch array");
-    if (ms == QP_MEM_HOST) std::memcpy(dst.data(), src, (size_t)count * sizeof(T));
-    else HIPCHK(hipMemcpy(dst.data(), src, (size_t)count * sizeof(T), hipMemcpyDeviceToHost));
+    if (ms == QP_MEM_HOST) {
+        dst.assign(src, src + count);  // one pass, no zero fill before the copy
+    } else {
+        dst.resize((size_t)count);
+        HIPCHK(hipMemcpy(dst.data(), src, (size_t)count * sizeof(T), hipMemcpyDeviceToHost));
+    }
     return QP_OK;
 }
 
