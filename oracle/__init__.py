@@ -33,4 +33,6 @@ from .oracle import (  # noqa: F401
     precondition,
     solve_scaled,
     infeas_check,
+    set_threads,
+    get_threads,
 )

@@ -1,7 +1,8 @@
 """Compile the CPU oracle (plain C, FP64) into oracle/liboracle.so.
 
 Test infrastructure only.  gcc, no fast-math and no FMA contraction, so each
-floating-point operation in the source is one IEEE operation.
+floating-point operation in the source is one IEEE operation.  OpenMP is linked
+for the threaded timing mode (orc_set_threads); the default is one thread.
 """
 import os
 import subprocess
@@ -14,7 +15,7 @@ OUT = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=199309L", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wextra", "-fPIC", "-shared", "-o", OUT + ".tmp", SRC,
+           "-fno-fast-math", "-fopenmp", "-Wall", "-Wextra", "-fPIC", "-shared", "-o", OUT + ".tmp", SRC,
            "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

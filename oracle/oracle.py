@@ -106,6 +106,8 @@ def load():
             from .build import build
             build()
         lib = C.CDLL(LIB_PATH)
+        lib.orc_set_threads.argtypes = [C.c_int32]
+        lib.orc_get_threads.restype = C.c_int32
         lib.orc_spmv.argtypes = [C.c_int64, _pi, _pi, _pd, _pd, _pd]
         lib.orc_spmv_t.argtypes = [C.c_int64, C.c_int64, _pi, _pi, _pd, _pd, _pd]
         lib.orc_rel_kkt.argtypes = [C.POINTER(_Problem), _pd, _pd, C.POINTER(_Kkt)]
@@ -133,6 +135,15 @@ def load():
         lib.orc_solve_scaled.restype = C.c_int
         _lib = lib
     return _lib
+
+
+def set_threads(t: int) -> None:
+    """Host threads for the row loops of later solves (bitwise the one-thread results)."""
+    load().orc_set_threads(int(t))
+
+
+def get_threads() -> int:
+    return int(load().orc_get_threads())
 
 
 def _f64(a):

@@ -10,8 +10,16 @@
  *   - fixed-frequency and "halving" restarts: Algorithm 1 and Sec. 5;
  *   - the Sec. 5 baselines: PDHG without momentum (beta = theta = 1) with and
  *     without restarts.
- * Everything is sequential and unblocked: each row sum runs in CSR order,
- * each dot product runs from index 0 upward.
+ * Everything is unblocked: each row sum runs in CSR order, each dot product
+ * runs from index 0 upward.  By default every loop is sequential.  For timing
+ * on a multi-core host, orc_set_threads(t > 1) runs the row loops of the
+ * matrix-vector products and the element-wise updates of the iteration on t
+ * OpenMP threads; each output element is still computed by one thread with the
+ * same operations in the same order (A'y then runs over a column-major copy of
+ * A whose column lists hold the entries in increasing row order, the order in
+ * which the sequential scatter adds them), so the results are bitwise those of
+ * one thread.  The reductions (norms, dot products, relKKT terms) stay
+ * sequential.
  */
 #include "rapdhg_oracle.h"
 
@@ -25,6 +33,12 @@ static double now_s(void) {
     clock_gettime(CLOCK_MONOTONIC, &ts);
     return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
 }
+
+static int g_threads = 1;
+
+void orc_set_threads(int32_t t) { g_threads = t < 1 ? 1 : t; }
+
+int32_t orc_get_threads(void) { return g_threads; }
 
 void orc_default_settings(orc_settings *s) {
     memset(s, 0, sizeof(*s));
@@ -55,6 +69,7 @@ void orc_default_settings(orc_settings *s) {
 /* ------------------------------------------------------------------ */
 void orc_spmv(int64_t nrows, const int32_t *rowptr, const int32_t *col, const double *val,
               const double *x, double *y) {
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
     for (int64_t i = 0; i < nrows; ++i) {
         double s = 0.0;
         for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
@@ -73,6 +88,50 @@ void orc_spmv_t(int64_t nrows, int64_t ncols, const int32_t *rowptr, const int32
             double prod = val[e] * x[i];
             y[col[e]] = y[col[e]] + prod;
         }
+    }
+}
+
+/* Column-major copy of an nrows x ncols CSR matrix: column j's entries in increasing
+ * row order (and, within a row, in stored order), with their row indices. */
+typedef struct {
+    int32_t *colptr, *row;
+    double *val;
+} orc_csc;
+
+static void csc_build(int64_t nrows, int64_t ncols, const int32_t *rowptr, const int32_t *col,
+                      const double *val, orc_csc *t) {
+    const int64_t nnz = rowptr[nrows];
+    t->colptr = calloc((size_t)ncols + 1, sizeof(int32_t));
+    t->row = malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    t->val = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    for (int64_t e = 0; e < nnz; ++e) t->colptr[col[e] + 1]++;
+    for (int64_t j = 0; j < ncols; ++j) t->colptr[j + 1] += t->colptr[j];
+    int32_t *next = malloc(sizeof(int32_t) * (size_t)(ncols > 0 ? ncols : 1));
+    for (int64_t j = 0; j < ncols; ++j) next[j] = t->colptr[j];
+    for (int64_t i = 0; i < nrows; ++i)
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            const int32_t q = next[col[e]]++;
+            t->row[q] = (int32_t)i;
+            t->val[q] = val[e];
+        }
+    free(next);
+}
+
+static void csc_free(orc_csc *t) {
+    free(t->colptr); free(t->row); free(t->val);
+}
+
+/* y = A'x through the column-major copy: the same products, added to y[j] in the
+ * same order as orc_spmv_t, one column per thread */
+static void spmv_t_csc(int64_t ncols, const orc_csc *t, const double *x, double *y) {
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
+    for (int64_t j = 0; j < ncols; ++j) {
+        double s = 0.0;
+        for (int64_t q = t->colptr[j]; q < t->colptr[j + 1]; ++q) {
+            double prod = t->val[q] * x[t->row[q]];
+            s = s + prod;
+        }
+        y[j] = s;
     }
 }
 
@@ -279,6 +338,7 @@ typedef struct {
     int64_t n, m;
     double *x, *x_prev, *xbar, *y, *ybar;
     double *xt, *xmd, *ax, *g, *aty;
+    const orc_csc *at;  /* column-major copy of A for threaded runs, or NULL */
 } orc_state;
 
 static void state_alloc(orc_state *st, int64_t n, int64_t m) {
@@ -287,6 +347,7 @@ static void state_alloc(orc_state *st, int64_t n, int64_t m) {
     st->x = malloc(nn); st->x_prev = malloc(nn); st->xbar = malloc(nn);
     st->xt = malloc(nn); st->xmd = malloc(nn); st->g = malloc(nn); st->aty = malloc(nn);
     st->y = malloc(mm); st->ybar = malloc(mm); st->ax = malloc(mm);
+    st->at = NULL;
 }
 
 static void state_free(orc_state *st) {
@@ -314,19 +375,23 @@ static void one_iteration(const orc_problem *p, orc_state *st, int momentum, int
         a = 1.0 / (double)(k + 1);
     }
     /* x_md = (1 - 1/beta) xbar + (1/beta) x ;  x~ = x + theta (x - x_prev) */
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
     for (int64_t j = 0; j < n; ++j) {
         st->xmd[j] = (1.0 - w) * st->xbar[j] + w * st->x[j];
         st->xt[j] = st->x[j] + theta * (st->x[j] - st->x_prev[j]);
     }
     /* dual step: y+ = proj_Y(y - d (A x~ - b)) */
     orc_spmv(m, p->a_rowptr, p->a_col, p->a_val, st->xt, st->ax);
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
     for (int64_t i = 0; i < m; ++i) {
         double yn = st->y[i] - dk * (st->ax[i] - p->b[i]);
         st->y[i] = proj_dual(yn, p->row_type[i]);
     }
     /* primal step: x+ = proj_X(x - p (Q x_md + c - A' y+)) */
     orc_spmv(n, p->q_rowptr, p->q_col, p->q_val, st->xmd, st->g);
-    orc_spmv_t(m, n, p->a_rowptr, p->a_col, p->a_val, st->y, st->aty);
+    if (st->at) spmv_t_csc(n, st->at, st->y, st->aty);
+    else orc_spmv_t(m, n, p->a_rowptr, p->a_col, p->a_val, st->y, st->aty);
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
     for (int64_t j = 0; j < n; ++j) {
         double grad = st->g[j] + p->c[j] - st->aty[j];
         double xn = proj_box(st->x[j] - pk * grad, p->l[j], p->u[j]);
@@ -334,6 +399,7 @@ static void one_iteration(const orc_problem *p, orc_state *st, int momentum, int
         st->x[j] = xn;
         st->xbar[j] = (1.0 - a) * st->xbar[j] + a * xn;
     }
+#pragma omp parallel for num_threads(g_threads) if (g_threads > 1) schedule(static)
     for (int64_t i = 0; i < m; ++i) st->ybar[i] = (1.0 - a) * st->ybar[i] + a * st->y[i];
 }
 
@@ -479,6 +545,11 @@ static int solve_impl(const orc_problem *p, const orc_problem *orig, const doubl
 
     orc_state st;
     state_alloc(&st, n, m);
+    orc_csc at;
+    if (g_threads > 1 && m > 0) {
+        csc_build(m, n, p->a_rowptr, p->a_col, p->a_val, &at);
+        st.at = &at;
+    }
     double *xu = malloc(sizeof(double) * (size_t)n);
     double *yu = malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
     double *x_rs = malloc(sizeof(double) * (size_t)n);
@@ -650,6 +721,7 @@ static int solve_impl(const orc_problem *p, const orc_problem *orig, const doubl
     res->used_warm_start = used_warm;
     if (log_len) *log_len = nlog < log_cap ? nlog : log_cap;
     free(x_rs); free(y_rs); free(xu); free(yu);
+    if (st.at) csc_free(&at);
     state_free(&st);
     return 0;
 }

@@ -148,6 +148,12 @@ int orc_solve_scaled(const orc_problem *scaled, const orc_problem *orig, const d
                      orc_result *res, orc_check_log *check_log, int64_t log_cap,
                      int64_t *log_len);
 
+/* Host threads for the row loops of a solve (timing on multi-core hosts; default 1).
+ * Results are bitwise those of one thread: every output element is computed by one
+ * thread in the sequential order, and every reduction stays sequential. */
+void orc_set_threads(int32_t t);
+int32_t orc_get_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -178,6 +178,95 @@ def test_three_iterations_hand_worked(orc):
             assert got[0] == pytest.approx(num / den, rel=1e-14), (it["k"], key)
 
 
+def _golden_qp(P):
+    return qp_refs.make_qp(P["Q"], P["A"], P["c"], P["b"], _inf(P["l"]), _inf(P["u"]),
+                           P["row_type"])
+
+
+def _frac(v):
+    return v[0] / v[1]
+
+
+def test_primal_weight_init_and_update_hand_worked(orc):
+    """Sec. 6 InitializePrimalWeight and PrimalWeightUpdate pinned by an exact-fraction hand
+    computation: omega0 = ||c||/||b||, the first iterate it yields through the step-size rule,
+    the tie-broken candidate, restart (iii) at the first evaluation, and
+    omega1 = (dy/dx)^theta * omega0^(1 - theta) with theta = 0.2."""
+    g = json.load(open(os.path.join(GOLDEN, "primal_weight_first_restart.json")))
+    qp = _golden_qp(g["problem"])
+    base = dict(eps=0.0, check_every=g["check_every"], norm_A=g["norm_A"], norm_Q=g["norm_Q"])
+    # one iteration, stopped at the limit before any restart: the weight is still omega0
+    x, y, r, log = orc.solve(qp, orc.OracleSettings(max_iter=1, **base), log_cap=8)
+    assert r["status"] == orc.ITERATION_LIMIT and r["restarts"] == 0
+    assert r["omega"] == pytest.approx(_frac(g["omega0"]), rel=1e-15)
+    assert x[0] == pytest.approx(_frac(g["x1"]), rel=1e-14)
+    assert y[0] == pytest.approx(_frac(g["y1"]), rel=1e-14)
+    assert r["rel_kkt"] == pytest.approx(_frac(g["rel_kkt_z1"]), rel=1e-13)
+    # two iterations: the evaluation after the first restarts and updates the weight
+    _, _, r2, log2 = orc.solve(qp, orc.OracleSettings(max_iter=2, **base), log_cap=8)
+    e = log2[0]
+    fc = g["first_check"]
+    assert (e["total"], e["candidate"], e["restarted"]) == (fc["total"], fc["candidate"],
+                                                            fc["restarted"])
+    assert e["r_cur"] == e["r_avg"] == pytest.approx(_frac(g["rel_kkt_z1"]), rel=1e-13)
+    w = g["omega1"]
+    th = _frac(w["theta"])
+    omega1 = _frac(w["ratio"]) ** th * _frac(w["omega0"]) ** (1.0 - th)
+    assert e["omega"] == pytest.approx(omega1, rel=1e-14)
+    assert r2["restarts"] >= 1
+
+
+def test_halving_first_check_hand_worked(orc):
+    """Sec. 5 halving rule at the first evaluation, from exact-fraction hand computations:
+    one case where relKKT of the average falls below half of relKKT(z0) (restart, to the
+    average) and one where it stays above it (no restart)."""
+    g = json.load(open(os.path.join(GOLDEN, "halving_first_check.json")))
+    for case in g["cases"]:
+        qp = _golden_qp(case["problem"])
+        s = orc.OracleSettings(eps=0.0, max_iter=2, check_every=1, norm_A=case["norm_A"],
+                               norm_Q=case["norm_Q"], restart_mode=orc.RESTART_HALVING)
+        _, _, r, log = orc.solve(qp, s, log_cap=8)
+        e = log[0]
+        assert e["total"] == 1
+        assert e["r_avg"] == pytest.approx(_frac(case["rel_kkt_zbar1"]), rel=1e-13)
+        assert e["restarted"] == case["restarted"], case["derivation"]
+        if case["restarted"]:
+            assert e["candidate"] == 1  # the restart point is the average
+        if "x1" in case:
+            x, y, r1, _ = orc.solve(qp, orc.OracleSettings(
+                eps=0.0, max_iter=1, check_every=1, norm_A=case["norm_A"], norm_Q=case["norm_Q"],
+                restart_mode=orc.RESTART_HALVING), log_cap=8)
+            assert x[0] == pytest.approx(_frac(case["x1"]), rel=1e-14)
+            assert y[0] == pytest.approx(_frac(case["y1"]), rel=1e-14)
+        r0 = orc.rel_kkt(qp, np.zeros(1), np.zeros(1))["rel_kkt"]
+        assert r0 == pytest.approx(_frac(case["rel_kkt_z0"]), rel=1e-15)
+
+
+def test_halving_log_replay(orc):
+    """Over a whole halving-restarted solve, every evaluation restarts exactly when
+    relKKT(z-bar) <= relKKT(z^{n,0}) / 2, always to the average, and the next cycle's
+    reference is the restart point's relKKT (Sec. 5)."""
+    held = 0  # evaluations after a restart that do not restart: they see the new reference
+    for seed in (2, 7):
+        qp = qpgen.tiny_random_qp(seed)
+        s = orc.OracleSettings(eps=1e-8, restart_mode=orc.RESTART_HALVING)
+        _, _, r, log = orc.solve(qp, s, log_cap=100000)
+        r0 = orc.rel_kkt(qp, np.clip(np.zeros(qp.n), qp.l, qp.u), np.zeros(qp.m))["rel_kkt"]
+        nrs = 0
+        for e in log[:-1]:
+            want = e["r_avg"] <= 0.5 * r0
+            assert bool(e["restarted"]) == want, (seed, e, r0)
+            if want:
+                assert e["candidate"] == 1
+                r0 = e["r_avg"]
+                nrs += 1
+            elif nrs:
+                held += 1
+        assert nrs >= 3 and r["restarts"] == nrs
+        assert r["status"] == orc.OPTIMAL
+    assert held >= 2
+
+
 def test_averaging_identity(orc):
     """With 1/beta_k = 2/(k+2): x-bar^K = sum_{i=1..K} 2i/(K(K+1)) x^i."""
     qp = qpgen.tiny_random_qp(2)
