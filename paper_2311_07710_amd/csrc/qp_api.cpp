@@ -329,6 +329,9 @@ int fetch(std::vector<T> &dst, const T *src, int64_t count, int mem_space) {
         dst.clear();
         return QP_OK;
     }
+    if (!src)
+        return fail(QP_ERR_INVALID_ARGUMENT, "null input array where %lld elements are expected",
+                    (long long)count);
     if (mem_space == QP_MEM_HOST) {
         dst.assign(src, src + count);  // one pass, no zero fill before the copy
     } else {
@@ -623,6 +626,8 @@ int gather_single(const qp_problem_desc *d, HostProblem &hp, const qp_settings &
     if (m > 0) {
         if (!d->A.row_ptr || !d->b)
             return fail(QP_ERR_INVALID_ARGUMENT, "A.row_ptr and b are required when m > 0");
+        if (d->A.nnz > 0 && (!d->A.col_idx || !d->A.val))
+            return fail(QP_ERR_INVALID_ARGUMENT, "A.col_idx and A.val are required when A.nnz > 0");
         if ((rc = fetch(ar, d->A.row_ptr, m + 1, ms))) return rc;
         if (ar[m] != d->A.nnz || d->A.nnz < 0)
             return fail(QP_ERR_INVALID_ARGUMENT, "A.nnz (%lld) disagrees with A.row_ptr[m] (%d)",

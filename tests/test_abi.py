@@ -150,6 +150,20 @@ def test_null_arguments():
     assert "null" in lib.qp_last_error().decode()
 
 
+@pytest.mark.parametrize("field", ["col_idx", "val"])
+def test_null_matrix_arrays_rejected_on_host(field):
+    """A null A.col_idx or A.val with A.nnz > 0 is an argument error, not a host crash."""
+    lib = qpa.load()
+    keep = _Keep(False)
+    d = _desc(_tiny(), keep, batch=False)
+    assert d.A.nnz > 0
+    setattr(d.A, field, None)
+    h = C.c_void_p()
+    rc = lib.qp_create(C.byref(d), C.byref(Settings().c_struct()), C.byref(h))
+    assert rc == B.QP_ERR_INVALID_ARGUMENT
+    assert "A.col_idx and A.val are required" in lib.qp_last_error().decode()
+
+
 def _batch_create_rc(batch, **settings):
     lib = qpa.load()
     keep = _Keep(False)
