@@ -52,6 +52,22 @@ int qp_mlp_get_grads(qp_mlp *h, float *grads);
 /* out[batch x sizes[L]] = network(x[batch x sizes[0]]); keeps the activations
  * for a following qp_mlp_backward. */
 int qp_mlp_forward(qp_mlp *h, const float *x, int32_t batch, float *out);
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the inference part of
+ * qp_mlp_forward with every temporary (BF16 activations, split-K partial tiles) in a
+ * fixed workspace of QP_MLP_NOALLOC_SCRATCH_BYTES that the library holds in static
+ * device memory, one per GPU until the process ends, located by qp_mlp_create; the
+ * call allocates nothing.  out[batch x sizes[L]] (device, FP32) receives the values
+ * qp_mlp_forward returns for the same x.  The activations are not kept (no
+ * qp_mlp_backward may rely on this call) and no buffer of the handle is written.
+ * Every call on one GPU shares its workspace, which keeps the last call's contents:
+ * calls that overlap in time on the same GPU (from other threads or handles) race,
+ * and the caller must serialise them.  A batch whose workspace would exceed the limit
+ * (2 x batch x the widest padded layer input in BF16, plus the split-K partials) is
+ * rejected with QP_ERR_INVALID_ARGUMENT before any device work.  Blocking on the
+ * handle's stream, like qp_mlp_forward. */
+#define QP_MLP_NOALLOC_SCRATCH_BYTES (32u << 20)
+int qp_mlp_forward_noalloc(qp_mlp *h, const float *x, int32_t batch, float *out);
 /* gradient of the mean squared error against target[batch x sizes[L]] at the
  * activations of the last forward call (same batch); *loss receives the loss. */
 int qp_mlp_backward(qp_mlp *h, const float *target, int32_t batch, float *loss);

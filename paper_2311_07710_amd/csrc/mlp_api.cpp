@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/qp_mlp.h"
@@ -16,6 +17,38 @@ using qph::fail;
 using namespace mlpk;
 
 static int pad32(int v) { return (v + 31) / 32 * 32; }
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Workspace of qp_mlp_forward_noalloc: static device memory, one copy per GPU for the
+// life of the process.  In host code `scratch` names a host-side stand-in, not a device
+// address; its address on each device comes from hipGetSymbolAddress, taken once per
+// device by qp_mlp_create with that device current, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[QP_MLP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[MAX_DEVICES];
+
+// the calling thread's current device must be `device`
+static int scratch_setup(int device) {
+    if (device < 0 || device >= MAX_DEVICES)
+        return fail(QP_ERR_INVALID_ARGUMENT, "device %d out of range", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return QP_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(QP_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", device,
+                    hipGetErrorString(e));
+    g_scratch_dev[device] = ptr;
+    return QP_OK;
+}
+
+static void *scratch_of(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[device];
+}
 
 struct qp_mlp {
     int L = 0;
@@ -60,6 +93,7 @@ int qp_mlp_create(int32_t n_layers, const int32_t *sizes, int32_t max_batch, int
     for (int i = 0; i <= n_layers; ++i)
         if (sizes[i] < 1) return fail(QP_ERR_INVALID_ARGUMENT, "layer size must be >= 1");
     HIPCHK(hipSetDevice(device));
+    if (int rc0 = scratch_setup(device)) return rc0;
     qp_mlp *h = new qp_mlp();
     h->L = n_layers;
     h->device = device;
@@ -189,6 +223,51 @@ int qp_mlp_forward(qp_mlp *h, const float *x, int32_t batch, float *out) {
         HIPCHK(hipMemcpyAsync(out, h->outf.p, (size_t)batch * h->sz[h->L] * 4,
                               hipMemcpyDeviceToDevice, s));
     h->lastB = batch;
+    HIPCHK(hipStreamSynchronize(s));
+    return QP_OK;
+}
+
+int qp_mlp_forward_noalloc(qp_mlp *h, const float *x, int32_t batch, float *out) {
+    if (!h || !x || !out) return fail(QP_ERR_INVALID_ARGUMENT, "null argument");
+    if (batch < 1 || batch > h->maxB) return fail(QP_ERR_INVALID_ARGUMENT, "batch out of range");
+    // workspace: BF16 activations of even layers' inputs, of odd layers' inputs, and the
+    // split-K partial tiles of the largest product
+    size_t act[2] = {0, 0}, part = 0;
+    for (int l = 0; l < h->L; ++l) {
+        act[l & 1] = std::max(act[l & 1], (size_t)batch * h->pad[l] * 2);
+        const int N = h->sz[l + 1];
+        part = std::max(part, (size_t)splitk_for(batch, N, h->pad[l]) * batch * N * 4);
+    }
+    const size_t off1 = align256(act[0]), offp = off1 + align256(act[1]);
+    const size_t need = offp + part;
+    if (need > (size_t)QP_MLP_NOALLOC_SCRATCH_BYTES)
+        return fail(QP_ERR_INVALID_ARGUMENT,
+                    "qp_mlp_forward_noalloc: batch %d needs %zu bytes of workspace, above the "
+                    "%zu-byte limit",
+                    (int)batch, need, (size_t)QP_MLP_NOALLOC_SCRATCH_BYTES);
+    HIPCHK(hipSetDevice(h->device));
+    unsigned char *ws = (unsigned char *)scratch_of(h->device);
+    if (!ws) return fail(QP_ERR_DEVICE, "no workspace address for device %d", h->device);
+    bf16 *bufs[2] = {(bf16 *)ws, (bf16 *)(ws + off1)};
+    float *pt = (float *)(ws + offp);
+    hipStream_t s = h->stream;
+    to_bf16(s, x, batch, h->sz[0], bufs[0], h->pad[0]);
+    for (int l = 0; l < h->L; ++l) {
+        const int N = h->sz[l + 1], K = h->pad[l];
+        const int S = splitk_for(batch, N, K);
+        gemm_nt(s, bufs[l & 1], K, h->Wb[l].as<bf16>(), K, pt, batch, N, K, S);
+        if (l == h->L - 1) {
+            reduce_epi(s, pt, S, batch, N, h->theta.as<float>() + h->b_off[l], 0, out, N,
+                       nullptr, 0);
+        } else {
+            bf16 *nx = bufs[(l + 1) & 1];
+            // the workspace keeps the previous call's contents: the K padding of the next
+            // layer's input must read as zeros
+            zero_pad_bf16(s, nx, batch, N, h->pad[l + 1]);
+            reduce_epi(s, pt, S, batch, N, h->theta.as<float>() + h->b_off[l], 1, nullptr, 0,
+                       nx, h->pad[l + 1]);
+        }
+    }
     HIPCHK(hipStreamSynchronize(s));
     return QP_OK;
 }

@@ -25,6 +25,7 @@ void relu_back(hipStream_t st, const float *dH, const bf16 *H, int ldh, int B, i
 void colsum(hipStream_t st, const float *dz, int B, int N, float *db);
 void adam(hipStream_t st, float *theta, const float *g, float *m, float *v, int64_t n, float lr,
           float b1, float b2, float eps, float c1, float c2, bf16 *wb, int cols, int ld);
+void zero_pad_bf16(hipStream_t st, bf16 *p, int rows, int c0, int ld);
 void weights_bf16(hipStream_t st, const float *w, int rows, int cols, bf16 *wb, int ld);
 
 }  // namespace mlpk

@@ -179,6 +179,15 @@ __global__ void k_adam(float *__restrict__ theta, const float *__restrict__ g, f
     }
 }
 
+// zeros in columns [c0, ld) of every row of a BF16 [rows x ld] matrix
+__global__ void k_zero_pad_bf16(bf16 *__restrict__ p, int rows, int c0, int ld) {
+    const int w = ld - c0;
+    const int64_t total = (int64_t)rows * w;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride)
+        p[(idx / w) * ld + c0 + idx % w] = (bf16)0.f;
+}
+
 // BF16 copy of a [rows x cols] FP32 block into [rows x ld] (zeros in the padding)
 __global__ void k_weights_bf16(const float *__restrict__ w, int rows, int cols,
                                bf16 *__restrict__ wb, int ld) {
@@ -253,6 +262,12 @@ void adam(hipStream_t st, float *theta, const float *g, float *m, float *v, int6
           float b1, float b2, float eps, float c1, float c2, bf16 *wb, int cols, int ld) {
     hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, st, theta, g, m, v, n, lr, b1, b2,
                        eps, c1, c2, wb, cols, ld);
+}
+
+void zero_pad_bf16(hipStream_t st, bf16 *p, int rows, int c0, int ld) {
+    if (c0 >= ld || rows < 1) return;
+    hipLaunchKernelGGL(k_zero_pad_bf16, dim3(grid_for((int64_t)rows * (ld - c0))), dim3(256), 0,
+                       st, p, rows, c0, ld);
 }
 
 void weights_bf16(hipStream_t st, const float *w, int rows, int cols, bf16 *wb, int ld) {

@@ -54,6 +54,18 @@ class MLP:
         B.check(self.lib.qp_mlp_forward(self.h, x.data_ptr(), x.shape[0], out.data_ptr()))
         return out
 
+    def forward_noalloc(self, x, out=None):
+        """Inference through qp_mlp_forward_noalloc (workspace in the library's static
+        device memory; no activations kept for backward)."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+        if out is None:
+            out = torch.empty(x.shape[0], self.sizes[-1], dtype=torch.float32, device=x.device)
+        assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+        torch.cuda.current_stream().synchronize()
+        B.check(self.lib.qp_mlp_forward_noalloc(self.h, x.data_ptr(), x.shape[0], out.data_ptr()))
+        return out
+
     def backward(self, target) -> float:
         import torch
         assert target.is_cuda and target.dtype == torch.float32 and target.is_contiguous()
