@@ -382,6 +382,8 @@ struct qp_handle {
     Csr A{}, P{};
     double norm_A = 0.0, norm_Q = 0.0, c_inf = 0.0, b_inf = 0.0, c_norm2 = 0.0, b_norm2 = 0.0;
     double dual_bytes = 0.0, primal_bytes = 0.0;  // algorithmic HBM bytes of one launch
+    int32_t uniform_bounds = 0;
+    double lo_all = 0.0, hi_all = 0.0;
 
     // solver vectors
     DevMem x, xbar, xt, xmd0, xmd1, xrs, y, ybar, yrs, x0buf, y0buf;
@@ -585,6 +587,14 @@ int upload_vectors(qp_handle *h, const std::vector<double> &c, const std::vector
                 us[j] = (*u)[j] / h->h_d[j];
             }
         if ((rc = put(h->l, ls)) || (rc = put(h->u, us))) return rc;
+        // bounds equal for every variable (x >= 0, or all free) let the primal epilogue
+        // skip reading l and u; compared bitwise, so -0.0 and 0.0 count as different
+        bool uni = n > 0;
+        for (int64_t j = 1; j < n && uni; ++j)
+            uni = std::memcmp(&ls[j], &ls[0], 8) == 0 && std::memcmp(&us[j], &us[0], 8) == 0;
+        h->uniform_bounds = uni ? 1 : 0;
+        h->lo_all = uni ? ls[0] : 0.0;
+        h->hi_all = uni ? us[0] : 0.0;
     }
     double cn = 0.0, bn = 0.0, ci = 0.0, bi = 0.0;
     for (int64_t j = 0; j < n; ++j) {
@@ -789,8 +799,9 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
         const double annz = (double)(m > 0 ? d->A.nnz : 0);
         h->dual_bytes = m > 0 ? 12.0 * annz + 4.0 * (double)(m + 1) + 8.0 * (double)gA +
                                     41.0 * (double)m : 0.0;
+        // (with bounds equal for every variable, l and u are two scalars: 56 B per row)
         h->primal_bytes = 12.0 * (double)pnnz + 4.0 * (double)(n + 1) + 8.0 * (double)gP +
-                          72.0 * (double)n;
+                          (h->uniform_bounds ? 56.0 : 72.0) * (double)n;
     }
     if ((rc = h->partA.upload(hpA)) || (rc = h->partP.upload(hpP))) return rc;
     h->npA = m > 0 ? choose_panels(h->set.panels_dual, n) : 1;
@@ -805,6 +816,13 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
         if (ta.joinable()) ta.join();
         if (h->npA > 1 && (rc = h->panA.upload(pa, m))) return rc;
         if (h->npP > 1 && (rc = h->panP.upload(pp, n))) return rc;
+        if (h->npA > 1 || h->npP > 1) {
+            const int32_t nwg = panel_resident_workgroups(h->device);
+            if (nwg < 8)
+                return fail(QP_ERR_DEVICE, "occupancy query of the panel kernels failed");
+            h->panA.view.nwg = nwg;
+            h->panP.view.nwg = nwg;
+        }
     }
 
     // solver vectors
@@ -846,6 +864,9 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
     v.rt = h->rt.as<uint8_t>();
     v.dv = h->h_d.empty() ? nullptr : h->dscale.as<double>();
     v.dr = h->h_d.empty() ? nullptr : h->dscale.as<double>() + n;
+    v.uniform_bounds = h->uniform_bounds;
+    v.lo_all = h->lo_all;
+    v.hi_all = h->hi_all;
     return QP_OK;
 }
 

@@ -58,6 +58,7 @@ struct Panels {
     double *lr_partial;       // [nblk * 4]
     double *part;             // [np * R]
     int32_t np, nblk, grid, nlr;
+    int32_t nwg;              // persistent workgroups of the hot panel kernels (multiple of 8)
     int64_t R;
 };
 
@@ -132,6 +133,8 @@ struct Vecs {
     const double *c, *b, *l, *u;
     const uint8_t *rt;
     const double *dv, *dr;                // preconditioning D2 [n], D1 [m], or nullptr
+    int32_t uniform_bounds;               // 1: l_j = lo_all and u_j = hi_all for every j
+    double lo_all, hi_all;
 };
 
 // ---- infeasibility certificates (qp_kernels.hip) ----
@@ -185,7 +188,9 @@ void launch_init(hipStream_t s, const Vecs &v, const double *x0, const double *y
 void launch_fallback_apply(hipStream_t s, const Vecs &v, const State *st, int64_t n, int64_t m);
 void launch_state_reset(hipStream_t s, State *st, double omega, int64_t max_iter);
 
-// column-panel phases (partials + combine)
+// column-panel phases (partials + combine); panel_resident_workgroups: workgroups of the
+// persistent panel kernels resident at once on `device` (a multiple of 8; 0 on error)
+int32_t panel_resident_workgroups(int device);
 void launch_dual_panels(hipStream_t s, const Panels &pn, const Vecs &v, int64_t n,
                         const Step *step, const State *st);
 void launch_primal_panels(hipStream_t s, const Panels &pn, const Vecs &v, int md_in, int64_t n,

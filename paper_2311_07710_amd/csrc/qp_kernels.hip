@@ -239,14 +239,33 @@ struct PrimalArgs {
     const double *y;
     double *x, *xbar, *xt, *xmd_out;
     const double *c, *l, *u;
+    int32_t ub;      // 1: every l_j = lo and every u_j = hi (l and u are not read)
+    double lo, hi;
 };
+
+static PrimalArgs primal_args(const Vecs &v, int md_in) {
+    PrimalArgs a;
+    a.xmd_in = v.xmd[md_in];
+    a.y = v.y;
+    a.x = v.x;
+    a.xbar = v.xbar;
+    a.xt = v.xt;
+    a.xmd_out = v.xmd[md_in ^ 1];
+    a.c = v.c;
+    a.l = v.l;
+    a.u = v.u;
+    a.ub = v.uniform_bounds;
+    a.lo = v.lo_all;
+    a.hi = v.hi_all;
+    return a;
+}
 
 __device__ __forceinline__ void primal_epilogue(int j, double s, const PrimalArgs &a, double p,
                                                 double w, double th1, double w1) {
     const double g = s + a.c[j];
     const double xo = a.x[j];
     double xn = xo - p * g;
-    const double lo = a.l[j], hi = a.u[j];
+    const double lo = a.ub ? a.lo : a.l[j], hi = a.ub ? a.hi : a.u[j];
     if (xn < lo) xn = lo;
     if (xn > hi) xn = hi;
     const double xb = (1.0 - w) * a.xbar[j] + w * xn;
@@ -1038,16 +1057,7 @@ void launch_dual(hipStream_t s, const Blocks &bk, const Csr &A, const Vecs &v, c
 void launch_primal(hipStream_t s, const Blocks &bk, const Csr &P, const Vecs &v, int md_in,
                    const Step *step, const State *st, int64_t n) {
     if (bk.nblk == 0) return;
-    PrimalArgs a;
-    a.xmd_in = v.xmd[md_in];
-    a.y = v.y;
-    a.x = v.x;
-    a.xbar = v.xbar;
-    a.xt = v.xt;
-    a.xmd_out = v.xmd[md_in ^ 1];
-    a.c = v.c;
-    a.l = v.l;
-    a.u = v.u;
+    const PrimalArgs a = primal_args(v, md_in);
     hipLaunchKernelGGL(k_primal, dim3(bk.nblk), dim3(BS), 0, s, bk, P, a, step, st, (int32_t)n);
 }
 
@@ -1221,60 +1231,121 @@ __device__ bool panel_chunk_finish(const Panels &pn, int bi, int lr, double part
 
 // PHASE 0: rows of A (dual phase, ordinary loads); PHASE 1: rows of P (primal phase,
 // non-temporal loads).  Gathers v1[c] for c < split and v2[c - split] otherwise.
+//
+// Persistent and software-pipelined: workgroup w walks the slots w, w + nwg, w + 2 nwg,
+// ... of the block map (nwg a multiple of 8, so every slot it takes belongs to its own
+// XCD).  For the current block it issues the gathers, then the loads of the current
+// block's values and of the NEXT block's column indices, so the matrix stream and the
+// random gathers of one workgroup are in flight together.  (With one block per workgroup
+// the blocks that start together stream together and then gather together: measured on
+// the large random QP, the stream alone took 42 us and the gathers alone about 75 us, and
+// the kernel took their sum.)  When there is no next block an empty range is loaded,
+// which reads the block's first entry and yields nothing.
+template <int SRC>
+__device__ __forceinline__ void load_cols(const int32_t *__restrict__ col, int e0, int e1, int t,
+                                          int (&cols)[EPT]) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = e0 + i * BS + t;
+        const int ee = e < e1 ? e : e0;
+        cols[i] = SRC == STREAM_P ? __builtin_nontemporal_load(&col[ee]) : col[ee];
+    }
+}
+
+template <int SRC>
+__device__ __forceinline__ void load_vals(const double *__restrict__ val, int e0, int e1, int t,
+                                          double (&vals)[EPT]) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = e0 + i * BS + t;
+        const int ee = e < e1 ? e : e0;
+        const double v = SRC == STREAM_P ? __builtin_nontemporal_load(&val[ee]) : val[ee];
+        vals[i] = e < e1 ? v : 0.0;
+    }
+}
+
+__device__ __forceinline__ int next_slot(const Panels &pn, int idx, int nwg) {
+    while (idx < pn.grid && pn.map[idx] < 0) idx += nwg;
+    return idx;
+}
+
 template <int PHASE>
 __global__ __launch_bounds__(BS) void k_panel_spmv(Panels pn, const double *__restrict__ v1,
                                                    const double *__restrict__ v2, int32_t split,
-                                                   const State *__restrict__ st) {
+                                                   int32_t nwg, const State *__restrict__ st) {
     if (st->done) return;
-    const int bi = pn.map[blockIdx.x];
-    if (bi < 0) return;
+    constexpr int SRC = PHASE == 0 ? STREAM_A : STREAM_P;
     __shared__ double prod[NNZ_BLK];
     __shared__ double scratch[BS / 64];
-    const PBlock B = pn.blk[bi];
     const int t = threadIdx.x;
+    int idx = next_slot(pn, blockIdx.x, nwg);
+    if (idx >= pn.grid) return;
+    int bi = pn.map[idx];
+    PBlock B = pn.blk[bi];
     int cols[EPT];
-    double vals[EPT];
-    load_block<PHASE == 0 ? STREAM_A : STREAM_P>(pn.col, pn.val, B.e0, B.e1, t, cols, vals);
-    double g[EPT];
+    load_cols<SRC>(pn.col, B.e0, B.e1, t, cols);
+    while (true) {
+        // next block's descriptor first: its loads complete together with this block's
+        // column indices, which the gathers need anyway
+        const int nidx = next_slot(pn, idx + nwg, nwg);
+        const bool more = nidx < pn.grid;
+        const int nbi = more ? pn.map[nidx] : bi;
+        const PBlock NB = pn.blk[nbi];
+        __builtin_amdgcn_sched_barrier(0);
+        double g[EPT];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int cc = cols[i];
-        if (PHASE == 0)
-            g[i] = v1[cc];
-        else
-            g[i] = *(cc < split ? v1 + cc : v2 + (cc - split));
-    }
+        for (int i = 0; i < EPT; ++i) {
+            const int cc = cols[i];
+            if (PHASE == 0)
+                g[i] = v1[cc];
+            else
+                g[i] = *(cc < split ? v1 + cc : v2 + (cc - split));
+        }
+        __builtin_amdgcn_sched_barrier(0);  // the gathers are issued before the stream loads
+        double vals[EPT];
+        load_vals<SRC>(pn.val, B.e0, B.e1, t, vals);
+        int ncols[EPT];
+        load_cols<SRC>(pn.col, NB.e0, more ? NB.e1 : NB.e0, t, ncols);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) prod[i * BS + t] = vals[i] * g[i];
-    __syncthreads();
-    const int32_t *rp = pn.rowptr + (size_t)B.panel * (size_t)(pn.R + 1);
-    double *out = pn.part + (size_t)B.panel * (size_t)pn.R;
-    if (B.lr < 0) {
-        const int nrows = B.row1 - B.row0;
-        if (nrows >= BS) {
-            for (int rl = t; rl < nrows; rl += BS) {
-                const int row = B.row0 + rl;
-                const int e1 = rp[row + 1] - B.e0;
+        for (int i = 0; i < EPT; ++i) prod[i * BS + t] = vals[i] * g[i];
+        __syncthreads();
+        const int32_t *rp = pn.rowptr + (size_t)B.panel * (size_t)(pn.R + 1);
+        double *out = pn.part + (size_t)B.panel * (size_t)pn.R;
+        if (B.lr < 0) {
+            const int nrows = B.row1 - B.row0;
+            if (nrows >= BS) {
+                for (int rl = t; rl < nrows; rl += BS) {
+                    const int row = B.row0 + rl;
+                    const int e1 = rp[row + 1] - B.e0;
+                    double s = 0.0;
+                    for (int e = rp[row] - B.e0; e < e1; ++e) s = s + prod[e];
+                    out[row] = s;
+                }
+            } else {
+                const int G = lanes_per_row(nrows);
+                const int rl = t / G, lane = t % G;
                 double s = 0.0;
-                for (int e = rp[row] - B.e0; e < e1; ++e) s = s + prod[e];
-                out[row] = s;
+                if (rl < nrows) {
+                    const int row = B.row0 + rl;
+                    const int e1 = rp[row + 1] - B.e0;
+                    for (int e = rp[row] - B.e0 + lane; e < e1; e += G) s = s + prod[e];
+                }
+                s = group_sum(s, G);
+                if (rl < nrows && lane == 0) out[B.row0 + rl] = s;
             }
         } else {
-            const int G = lanes_per_row(nrows);
-            const int rl = t / G, lane = t % G;
-            double s = 0.0;
-            if (rl < nrows) {
-                const int row = B.row0 + rl;
-                const int e1 = rp[row + 1] - B.e0;
-                for (int e = rp[row] - B.e0 + lane; e < e1; e += G) s = s + prod[e];
-            }
-            s = group_sum(s, G);
-            if (rl < nrows && lane == 0) out[B.row0 + rl] = s;
+            const double part = block_sum_lds(prod, B.e1 - B.e0, scratch);
+            double tot;
+            if (panel_chunk_finish(pn, bi, B.lr, part, &tot)) out[B.row0] = tot;
         }
-    } else {
-        const double part = block_sum_lds(prod, B.e1 - B.e0, scratch);
-        double tot;
-        if (panel_chunk_finish(pn, bi, B.lr, part, &tot)) out[B.row0] = tot;
+        if (!more) break;
+        __syncthreads();  // prod is rewritten by the next block
+        idx = nidx;
+        bi = nbi;
+        B = NB;
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) cols[i] = ncols[i];
     }
 }
 
@@ -1450,6 +1521,25 @@ __global__ __launch_bounds__(BS) void k_kkt_cols_combine(const double *__restric
     block_reduce_write<RP_NV, 6>(cv, a.partials + (size_t)blockIdx.x * RP_NV);
 }
 
+// Persistent workgroups of the panel phases: as many as can be resident at once (the
+// occupancy both phase kernels reach, times the CU count), a multiple of 8 so each keeps
+// to one XCD, at most the map size.
+int32_t panel_resident_workgroups(int device) {
+    int per_cu0 = 0, per_cu1 = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu0, k_panel_spmv<0>, BS, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, k_panel_spmv<1>, BS, 0) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    const int per_cu = per_cu0 < per_cu1 ? per_cu0 : per_cu1;
+    return (per_cu * cus) / 8 * 8;
+}
+
+static int32_t panel_workgroups(const Panels &pn) {
+    return pn.grid < pn.nwg ? pn.grid : pn.nwg;
+}
+
 int32_t launch_kkt_rows_panels(hipStream_t s, const Panels &pn, const Vecs &v, double *kpart,
                                double *partials, const State *st, int64_t n, int64_t m) {
     if (m == 0) return 0;
@@ -1500,27 +1590,20 @@ void launch_dual_panels(hipStream_t s, const Panels &pn, const Vecs &v, int64_t 
                         const Step *step, const State *st) {
     if (pn.R == 0) return;
     if (pn.grid > 0)
-        hipLaunchKernelGGL(k_panel_spmv<0>, dim3(pn.grid), dim3(BS), 0, s, pn, (const double *)v.xt,
-                           (const double *)nullptr, (int32_t)n, st);
+        hipLaunchKernelGGL(k_panel_spmv<0>, dim3(panel_workgroups(pn)), dim3(BS), 0, s, pn,
+                           (const double *)v.xt, (const double *)nullptr, (int32_t)n,
+                           panel_workgroups(pn), st);
     hipLaunchKernelGGL(k_dual_combine, dim3((unsigned)((pn.R + 255) / 256)), dim3(256), 0, s,
                        (const double *)pn.part, pn.np, pn.R, v.y, v.ybar, v.b, v.rt, step, st);
 }
 
 void launch_primal_panels(hipStream_t s, const Panels &pn, const Vecs &v, int md_in, int64_t n,
                           const Step *step, const State *st) {
-    PrimalArgs a;
-    a.xmd_in = v.xmd[md_in];
-    a.y = v.y;
-    a.x = v.x;
-    a.xbar = v.xbar;
-    a.xt = v.xt;
-    a.xmd_out = v.xmd[md_in ^ 1];
-    a.c = v.c;
-    a.l = v.l;
-    a.u = v.u;
+    const PrimalArgs a = primal_args(v, md_in);
     if (pn.grid > 0)
-        hipLaunchKernelGGL(k_panel_spmv<1>, dim3(pn.grid), dim3(BS), 0, s, pn,
-                           (const double *)v.xmd[md_in], (const double *)v.y, (int32_t)n, st);
+        hipLaunchKernelGGL(k_panel_spmv<1>, dim3(panel_workgroups(pn)), dim3(BS), 0, s, pn,
+                           (const double *)v.xmd[md_in], (const double *)v.y, (int32_t)n,
+                           panel_workgroups(pn), st);
     hipLaunchKernelGGL(k_primal_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        (const double *)pn.part, pn.np, n, a, step, st);
 }
