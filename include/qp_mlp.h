@@ -48,6 +48,10 @@ int64_t qp_mlp_num_params(const qp_mlp *h);
 int qp_mlp_set_params(qp_mlp *h, const float *params);
 int qp_mlp_get_params(qp_mlp *h, float *params);
 int qp_mlp_get_grads(qp_mlp *h, float *grads);
+/* replaces the gradient with a host FP32 array of qp_mlp_num_params entries (for
+ * example gradients summed over several replicas); a following qp_mlp_adam_step
+ * applies it. */
+int qp_mlp_set_grads(qp_mlp *h, const float *grads);
 
 /* out[batch x sizes[L]] = network(x[batch x sizes[0]]); keeps the activations
  * for a following qp_mlp_backward. */
@@ -71,6 +75,19 @@ int qp_mlp_forward_noalloc(qp_mlp *h, const float *x, int32_t batch, float *out)
 /* gradient of the mean squared error against target[batch x sizes[L]] at the
  * activations of the last forward call (same batch); *loss receives the loss. */
 int qp_mlp_backward(qp_mlp *h, const float *target, int32_t batch, float *loss);
+/* Minibatch forms for training on a data set resident in device memory: x_all
+ * [n_rows x sizes[0]] and target_all [n_rows x sizes[L]] (device, FP32, row-major)
+ * hold every sample, and rows (device, int32, batch entries) names the samples of
+ * the minibatch: sample i is row rows[i].  The rows are gathered by the kernels that
+ * read the data (BF16 conversion of the input, the loss gradient), so no copy of the
+ * minibatch is made.  An index outside [0, n_rows) yields QP_ERR_INVALID_ARGUMENT
+ * after the call (that sample is read as zeros); qp_mlp_backward_rows must follow a
+ * qp_mlp_forward_rows (or qp_mlp_forward) of the same batch size, and its rows should
+ * be the ones that forward used. */
+int qp_mlp_forward_rows(qp_mlp *h, const float *x_all, int64_t n_rows, const int32_t *rows,
+                        int32_t batch, float *out);
+int qp_mlp_backward_rows(qp_mlp *h, const float *target_all, int64_t n_rows,
+                         const int32_t *rows, int32_t batch, float *loss);
 /* one Adam step (bias-corrected, step >= 1) on every parameter with the current
  * gradients; refreshes the BF16 copies used by forward. */
 int qp_mlp_adam_step(qp_mlp *h, float lr, float beta1, float beta2, float eps, int32_t step);

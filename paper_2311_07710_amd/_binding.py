@@ -109,9 +109,13 @@ MLP_SIGNATURES = {
     "qp_mlp_set_params": (C.c_int, [_vp, _vp]),
     "qp_mlp_get_params": (C.c_int, [_vp, _vp]),
     "qp_mlp_get_grads": (C.c_int, [_vp, _vp]),
+    "qp_mlp_set_grads": (C.c_int, [_vp, _vp]),
     "qp_mlp_forward": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
+    "qp_mlp_forward_rows": (C.c_int, [_vp, _vp, C.c_int64, _vp, C.c_int32, _vp]),
     "qp_mlp_forward_noalloc": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
     "qp_mlp_backward": (C.c_int, [_vp, _vp, C.c_int32, C.POINTER(C.c_float)]),
+    "qp_mlp_backward_rows": (C.c_int, [_vp, _vp, C.c_int64, _vp, C.c_int32,
+                                       C.POINTER(C.c_float)]),
     "qp_mlp_adam_step": (C.c_int, [_vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32]),
 }
 

@@ -61,6 +61,7 @@ struct qp_mlp {
     DevMem theta, grad, m1, m2;
     std::vector<DevMem> Wb, WbT, H;
     DevMem outf, dzf, dzb, dzT, HT, dH, part, lpart;
+    DevMem bad;  // set by the row-gathering kernels when a row index is out of range
     size_t part_elems = 0;
     int lastB = 0;
     ~qp_mlp() {
@@ -149,9 +150,9 @@ int qp_mlp_create(int32_t n_layers, const int32_t *sizes, int32_t max_batch, int
         (rc = h->dzT.alloc((size_t)h->maxdim * h->Bpad * 2)) ||
         (rc = h->HT.alloc((size_t)h->maxdim * h->Bpad * 2)) ||
         (rc = h->dH.alloc((size_t)h->maxB * h->maxdim * 4)) || (rc = h->part.alloc(pe * 4)) ||
-        (rc = h->lpart.alloc(1024 * 8)))
+        (rc = h->lpart.alloc(1024 * 8)) || (rc = h->bad.alloc(4)))
         return done(rc);
-    DevMem *all[] = {&h->theta, &h->grad, &h->m1, &h->m2, &h->dzb, &h->dzT, &h->HT};
+    DevMem *all[] = {&h->theta, &h->grad, &h->m1, &h->m2, &h->dzb, &h->dzT, &h->HT, &h->bad};
     for (DevMem *d : all)
         if ((rc = zero(*d, h->stream))) return done(rc);
     for (auto &d : h->Wb)
@@ -203,12 +204,34 @@ int qp_mlp_get_grads(qp_mlp *h, float *grads) {
     return QP_OK;
 }
 
-int qp_mlp_forward(qp_mlp *h, const float *x, int32_t batch, float *out) {
-    if (!h || !x) return fail(QP_ERR_INVALID_ARGUMENT, "null argument");
-    if (batch < 1 || batch > h->maxB) return fail(QP_ERR_INVALID_ARGUMENT, "batch out of range");
+int qp_mlp_set_grads(qp_mlp *h, const float *grads) {
+    if (!h || !grads) return fail(QP_ERR_INVALID_ARGUMENT, "null argument");
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipMemcpyAsync(h->grad.p, grads, (size_t)h->nparams * 4, hipMemcpyHostToDevice,
+                          h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return QP_OK;
+}
+
+}  // extern "C"
+
+// reads the out-of-range flag of the row-gathering kernels (the stream is synchronised)
+static int check_rows(qp_mlp *h, const char *who) {
+    int32_t bad = 0;
+    HIPCHK(hipMemcpy(&bad, h->bad.p, 4, hipMemcpyDeviceToHost));
+    if (bad) {
+        HIPCHK(hipMemset(h->bad.p, 0, 4));
+        return fail(QP_ERR_INVALID_ARGUMENT, "%s: a row index is outside [0, n_rows)", who);
+    }
+    return QP_OK;
+}
+
+static int forward_impl(qp_mlp *h, const float *x, const int32_t *rows, int64_t n_rows,
+                        int32_t batch, float *out) {
     HIPCHK(hipSetDevice(h->device));
     hipStream_t s = h->stream;
-    to_bf16(s, x, batch, h->sz[0], h->H[0].as<bf16>(), h->pad[0]);
+    to_bf16(s, x, batch, h->sz[0], h->H[0].as<bf16>(), h->pad[0], rows, n_rows,
+            h->bad.as<int32_t>());
     for (int l = 0; l < h->L; ++l) {
         const int N = h->sz[l + 1], K = h->pad[l];
         const int S = splitk_for(batch, N, K);
@@ -222,9 +245,30 @@ int qp_mlp_forward(qp_mlp *h, const float *x, int32_t batch, float *out) {
     if (out)
         HIPCHK(hipMemcpyAsync(out, h->outf.p, (size_t)batch * h->sz[h->L] * 4,
                               hipMemcpyDeviceToDevice, s));
-    h->lastB = batch;
     HIPCHK(hipStreamSynchronize(s));
+    int rc;
+    if (rows && (rc = check_rows(h, "qp_mlp_forward_rows"))) {
+        h->lastB = 0;
+        return rc;
+    }
+    h->lastB = batch;
     return QP_OK;
+}
+
+extern "C" {
+
+int qp_mlp_forward(qp_mlp *h, const float *x, int32_t batch, float *out) {
+    if (!h || !x) return fail(QP_ERR_INVALID_ARGUMENT, "null argument");
+    if (batch < 1 || batch > h->maxB) return fail(QP_ERR_INVALID_ARGUMENT, "batch out of range");
+    return forward_impl(h, x, nullptr, 0, batch, out);
+}
+
+int qp_mlp_forward_rows(qp_mlp *h, const float *x_all, int64_t n_rows, const int32_t *rows,
+                        int32_t batch, float *out) {
+    if (!h || !x_all || !rows) return fail(QP_ERR_INVALID_ARGUMENT, "null argument");
+    if (batch < 1 || batch > h->maxB) return fail(QP_ERR_INVALID_ARGUMENT, "batch out of range");
+    if (n_rows < 1) return fail(QP_ERR_INVALID_ARGUMENT, "n_rows must be >= 1");
+    return forward_impl(h, x_all, rows, n_rows, batch, out);
 }
 
 int qp_mlp_forward_noalloc(qp_mlp *h, const float *x, int32_t batch, float *out) {
@@ -272,15 +316,17 @@ int qp_mlp_forward_noalloc(qp_mlp *h, const float *x, int32_t batch, float *out)
     return QP_OK;
 }
 
-int qp_mlp_backward(qp_mlp *h, const float *target, int32_t batch, float *loss) {
-    if (!h || !target) return fail(QP_ERR_INVALID_ARGUMENT, "null argument");
-    if (batch != h->lastB) return fail(QP_ERR_INVALID_ARGUMENT, "backward needs the last forward batch");
+}  // extern "C"
+
+static int backward_impl(qp_mlp *h, const float *target, const int32_t *rows, int64_t n_rows,
+                         int32_t batch, float *loss) {
     HIPCHK(hipSetDevice(h->device));
     hipStream_t s = h->stream;
     const int L = h->L, NO = h->sz[L];
     const float coef = 2.0f / ((float)batch * (float)NO);
     const int nb = mse_grad(s, h->outf.as<float>(), target, batch, NO, coef, h->dzf.as<float>(),
-                            h->dzb.as<bf16>(), h->pad[L], h->lpart.as<double>());
+                            h->dzb.as<bf16>(), h->pad[L], h->lpart.as<double>(), rows, n_rows,
+                            h->bad.as<int32_t>());
     for (int l = L - 1; l >= 0; --l) {
         const int No = h->sz[l + 1], Ni = h->sz[l];
         // dW_l = dZ_l' H_l  (K = batch)
@@ -293,7 +339,9 @@ int qp_mlp_backward(qp_mlp *h, const float *target, int32_t batch, float *loss) 
                 h->part.as<float>(), No, Ni, pad32(batch), S);
         reduce_epi(s, h->part.as<float>(), S, No, Ni, nullptr, 0,
                    h->grad.as<float>() + h->w_off[l], Ni, nullptr, 0);
-        colsum(s, h->dzf.as<float>(), batch, No, h->grad.as<float>() + h->b_off[l]);
+        // the split-K partial buffer is free between the dW and dH products
+        colsum(s, h->dzf.as<float>(), batch, No, h->part.as<float>(),
+               h->grad.as<float>() + h->b_off[l]);
         if (l > 0) {
             // dH_l = dZ_l W_l, then the ReLU mask of H_l
             S = splitk_for(batch, Ni, h->pad[l + 1]);
@@ -311,7 +359,26 @@ int qp_mlp_backward(qp_mlp *h, const float *target, int32_t batch, float *loss) 
     double acc = 0.0;
     for (double v : lp) acc += v;
     if (loss) *loss = (float)(acc / ((double)batch * NO));
+    if (rows) return check_rows(h, "qp_mlp_backward_rows");
     return QP_OK;
+}
+
+extern "C" {
+
+int qp_mlp_backward(qp_mlp *h, const float *target, int32_t batch, float *loss) {
+    if (!h || !target) return fail(QP_ERR_INVALID_ARGUMENT, "null argument");
+    if (batch < 1 || batch != h->lastB)
+        return fail(QP_ERR_INVALID_ARGUMENT, "backward needs the last forward batch");
+    return backward_impl(h, target, nullptr, 0, batch, loss);
+}
+
+int qp_mlp_backward_rows(qp_mlp *h, const float *target_all, int64_t n_rows,
+                         const int32_t *rows, int32_t batch, float *loss) {
+    if (!h || !target_all || !rows) return fail(QP_ERR_INVALID_ARGUMENT, "null argument");
+    if (batch < 1 || batch != h->lastB)
+        return fail(QP_ERR_INVALID_ARGUMENT, "backward needs the last forward batch");
+    if (n_rows < 1) return fail(QP_ERR_INVALID_ARGUMENT, "n_rows must be >= 1");
+    return backward_impl(h, target_all, rows, n_rows, batch, loss);
 }
 
 int qp_mlp_adam_step(qp_mlp *h, float lr, float beta1, float beta2, float eps, int32_t step) {

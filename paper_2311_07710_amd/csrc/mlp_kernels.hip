@@ -75,14 +75,26 @@ __global__ void k_reduce_epi(const float *__restrict__ part, int S, int M, int N
     }
 }
 
-// FP32 [rows x cols] -> BF16 [rows x ld] with zeros in columns [cols, ld)
+// FP32 [rows x cols] -> BF16 [rows x ld] with zeros in columns [cols, ld).  With `sel`,
+// row r of the output is row sel[r] of `in` (which has nsrc rows); an index outside
+// [0, nsrc) gives a zero row and sets *bad.
 __global__ void k_to_bf16(const float *__restrict__ in, int rows, int cols, bf16 *__restrict__ out,
-                          int ld) {
+                          int ld, const int32_t *__restrict__ sel, int64_t nsrc,
+                          int32_t *__restrict__ bad) {
     const int64_t total = (int64_t)rows * ld;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
         const int r = (int)(idx / ld), c = (int)(idx % ld);
-        out[idx] = c < cols ? (bf16)in[(size_t)r * cols + c] : (bf16)0.f;
+        int64_t src = r;
+        if (sel) {
+            src = sel[r];
+            if (src < 0 || src >= nsrc) {
+                *bad = 1;
+                out[idx] = (bf16)0.f;
+                continue;
+            }
+        }
+        out[idx] = c < cols ? (bf16)in[src * cols + c] : (bf16)0.f;
     }
 }
 
@@ -103,25 +115,37 @@ __global__ void k_transpose_bf16(const bf16 *__restrict__ in, int rows, int cols
     }
 }
 
-// dO = coef (O - T) (FP32 and padded BF16); per-block partial sums of (O - T)^2
+// dO = coef (O - T) (FP32 and padded BF16); per-block partial sums of (O - T)^2.  With
+// `sel`, the target of sample r is row sel[r] of T (nsrc rows); an index outside
+// [0, nsrc) gives a zero gradient row and sets *bad.
 __global__ __launch_bounds__(256) void k_mse_grad(const float *__restrict__ O,
                                                   const float *__restrict__ T, int B, int N,
                                                   float coef, float *__restrict__ dzf,
                                                   bf16 *__restrict__ dzb, int ldb,
-                                                  double *__restrict__ lpart) {
+                                                  double *__restrict__ lpart,
+                                                  const int32_t *__restrict__ sel, int64_t nsrc,
+                                                  int32_t *__restrict__ bad) {
     __shared__ double red[256];
     const int64_t total = (int64_t)B * ldb;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     double acc = 0.0;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
         const int r = (int)(idx / ldb), c = (int)(idx % ldb);
-        if (c < N) {
-            const float d = O[(size_t)r * N + c] - T[(size_t)r * N + c];
+        int64_t tr = r;
+        bool ok = true;
+        if (sel) {
+            tr = sel[r];
+            ok = tr >= 0 && tr < nsrc;
+            if (!ok) *bad = 1;
+        }
+        if (c < N && ok) {
+            const float d = O[(size_t)r * N + c] - T[tr * N + c];
             acc += (double)d * (double)d;
             const float g = coef * d;
             dzf[(size_t)r * N + c] = g;
             dzb[idx] = (bf16)g;
         } else {
+            if (c < N) dzf[(size_t)r * N + c] = 0.f;
             dzb[idx] = (bf16)0.f;
         }
     }
@@ -152,12 +176,31 @@ __global__ void k_relu_back(const float *__restrict__ dH, const bf16 *__restrict
     }
 }
 
-// db[j] = sum_b dZ[b][j] (rows in order)
-__global__ void k_colsum(const float *__restrict__ dz, int B, int N, float *__restrict__ db) {
+// db[j] = sum_b dZ[b][j] in two stages with a fixed order.  Stage 1: workgroup (x, y)
+// sums rows [64y, 64y + 64) of columns [64x, 64x + 64): lane q of column j adds rows
+// 64y + q, 64y + q + 4, ... in order, then the four lane sums are added in lane order
+// into part[y][j].  Stage 2 adds the row chunks in order.
+__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ dz, int B, int N,
+                                                     float *__restrict__ part) {
+    __shared__ float red[4][64];
+    const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + c;
+    const int r0 = blockIdx.y * 64, r1 = min(B, r0 + 64);
+    float s = 0.f;
+    if (j < N)
+        for (int r = r0 + q; r < r1; r += 4) s += dz[(size_t)r * N + j];
+    red[q][c] = s;
+    __syncthreads();
+    if (q == 0 && j < N)
+        part[(size_t)blockIdx.y * N + j] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+__global__ void k_colsum_fin(const float *__restrict__ part, int chunks, int N,
+                             float *__restrict__ db) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    float s = 0.f;
-    for (int b = 0; b < B; ++b) s += dz[(size_t)b * N + j];
+    float s = part[j];
+    for (int y = 1; y < chunks; ++y) s += part[(size_t)y * N + j];
     db[j] = s;
 }
 
@@ -229,9 +272,10 @@ void reduce_epi(hipStream_t st, const float *part, int S, int M, int N, const fl
                        N, bias, relu, outf, ldf, outb, ldb);
 }
 
-void to_bf16(hipStream_t st, const float *in, int rows, int cols, bf16 *out, int ld) {
+void to_bf16(hipStream_t st, const float *in, int rows, int cols, bf16 *out, int ld,
+             const int32_t *sel, int64_t nsrc, int32_t *bad) {
     hipLaunchKernelGGL(k_to_bf16, dim3(grid_for((int64_t)rows * ld)), dim3(256), 0, st, in, rows,
-                       cols, out, ld);
+                       cols, out, ld, sel, nsrc, bad);
 }
 
 void transpose_bf16(hipStream_t st, const bf16 *in, int rows, int cols, int ldi, bf16 *out,
@@ -241,10 +285,10 @@ void transpose_bf16(hipStream_t st, const bf16 *in, int rows, int cols, int ldi,
 }
 
 int mse_grad(hipStream_t st, const float *O, const float *T, int B, int N, float coef, float *dzf,
-             bf16 *dzb, int ldb, double *lpart) {
+             bf16 *dzb, int ldb, double *lpart, const int32_t *sel, int64_t nsrc, int32_t *bad) {
     const unsigned g = grid_for((int64_t)B * ldb) > 1024 ? 1024 : grid_for((int64_t)B * ldb);
     hipLaunchKernelGGL(k_mse_grad, dim3(g), dim3(256), 0, st, O, T, B, N, coef, dzf, dzb, ldb,
-                       lpart);
+                       lpart, sel, nsrc, bad);
     return (int)g;
 }
 
@@ -254,8 +298,11 @@ void relu_back(hipStream_t st, const float *dH, const bf16 *H, int ldh, int B, i
                        ldh, B, N, dzf, dzb, ldb);
 }
 
-void colsum(hipStream_t st, const float *dz, int B, int N, float *db) {
-    hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, st, dz, B, N, db);
+void colsum(hipStream_t st, const float *dz, int B, int N, float *part, float *db) {
+    const int chunks = (B + 63) / 64;
+    hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, chunks), dim3(256), 0, st, dz, B, N,
+                       part);
+    hipLaunchKernelGGL(k_colsum_fin, dim3((N + 255) / 256), dim3(256), 0, st, part, chunks, N, db);
 }
 
 void adam(hipStream_t st, float *theta, const float *g, float *m, float *v, int64_t n, float lr,

@@ -46,6 +46,33 @@ class MLP:
         B.check(self.lib.qp_mlp_get_grads(self.h, g.ctypes.data))
         return g
 
+    def set_grads(self, grads):
+        g = np.ascontiguousarray(grads, dtype=np.float32)
+        assert g.size == self.n_params
+        B.check(self.lib.qp_mlp_set_grads(self.h, g.ctypes.data))
+
+    def forward_rows(self, x_all, rows):
+        """Forward on the minibatch x_all[rows] (rows: CUDA int32 tensor), gathered by the
+        library's input conversion kernel."""
+        import torch
+        assert x_all.is_cuda and x_all.dtype == torch.float32 and x_all.is_contiguous()
+        assert rows.is_cuda and rows.dtype == torch.int32 and rows.is_contiguous()
+        out = torch.empty(rows.shape[0], self.sizes[-1], dtype=torch.float32, device=x_all.device)
+        torch.cuda.current_stream().synchronize()
+        B.check(self.lib.qp_mlp_forward_rows(self.h, x_all.data_ptr(), x_all.shape[0],
+                                             rows.data_ptr(), rows.shape[0], out.data_ptr()))
+        return out
+
+    def backward_rows(self, t_all, rows) -> float:
+        import torch
+        assert t_all.is_cuda and t_all.dtype == torch.float32 and t_all.is_contiguous()
+        assert rows.is_cuda and rows.dtype == torch.int32 and rows.is_contiguous()
+        torch.cuda.current_stream().synchronize()
+        loss = C.c_float()
+        B.check(self.lib.qp_mlp_backward_rows(self.h, t_all.data_ptr(), t_all.shape[0],
+                                              rows.data_ptr(), rows.shape[0], C.byref(loss)))
+        return float(loss.value)
+
     def forward(self, x):
         import torch
         assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()

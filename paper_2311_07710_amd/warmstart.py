@@ -119,14 +119,13 @@ def train(F: np.ndarray, T: np.ndarray, n: int, m: int, hidden=(512, 512), epoch
     hist = []
     N = F.shape[0]
     for ep in range(epochs):
-        perm = torch.from_numpy(rng.permutation(N)).cuda()
+        # the minibatch rows are gathered by the library's kernels (no device copy here)
+        perm = torch.from_numpy(rng.permutation(N).astype(np.int32)).cuda()
         tot, cnt = 0.0, 0
         for s in range(0, N - batch + 1, batch):
             sel = perm[s:s + batch]
-            xb = Zf.index_select(0, sel).contiguous()
-            tb = Zt.index_select(0, sel).contiguous()
-            mlp.forward(xb)
-            loss = mlp.backward(tb)
+            mlp.forward_rows(Zf, sel)
+            loss = mlp.backward_rows(Zt, sel)
             step += 1
             mlp.adam_step(lr=lr, step=step)
             tot += loss

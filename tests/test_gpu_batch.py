@@ -189,34 +189,63 @@ def test_batch_equals_single_solves(qpa):
                                    atol=1e-9)
 
 
-def test_batch_full_size_sampled(orc, qpa):
-    """The 4096-instance MPC batch the benchmark times (same launch configuration:
-    autotuned team sizes), checked instance by instance against the oracle on a sample
-    that includes the slowest instance of the set."""
+def _full_batch_sampled(orc, qpa, precondition):
+    """The 4096-instance MPC batch with autotuned team sizes, checked instance by instance
+    against the oracle on a sample that includes the instance needing the most iterations.
+    The sampled instances run with the oracle's own power-iteration norms (set on the
+    batch before the solve; the other instances keep the library's); with preprocessing
+    the oracle solves its own Sec. 5 scaling of each sampled instance."""
     batch = qpgen.mpc_batch(seed=4, count=4096)
-    bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6))
+    bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6, precondition=1 if precondition else 0))
     bs.autotune(sample=128, iters=256)
-    gA, gQ = bs.norms()
+    gA, gQ = (np.array(v, dtype=float) for v in bs.norms())
+    _, _, r0 = bs.solve()
+    its = np.array([r["iterations"] for r in r0])
+    slow = int(np.argmax(its))
+    sample = sorted({0, 1000, 2047, 3071, 4095, slow})
+    print(f"  slowest instance {slow}: {its[slow]} iterations (mean {its.mean():.0f})", flush=True)
+    ref = {}
+    for i in sample:
+        qp = batch.instance(i)
+        if precondition:
+            sc, dv, dr = orc.precondition(qp)
+            nA, _ = orc.norm_A(sc, 1000, 1e-7)
+            nQ, _ = orc.norm_Q(sc, 1000, 1e-7)
+            s = orc.OracleSettings(eps=1e-6, norm_A=nA, norm_Q=nQ)
+            ref[i] = orc.solve_scaled(sc, qp, dv, dr, s)[:3]
+        else:
+            nA, _ = orc.norm_A(qp, 1000, 1e-7)
+            nQ, _ = orc.norm_Q(qp, 1000, 1e-7)
+            ref[i] = orc.solve(qp, orc.OracleSettings(eps=1e-6, norm_A=nA, norm_Q=nQ))[:3]
+        gA[i], gQ[i] = nA, nQ
+    bs.set_norms(gA, gQ)
     xg, yg, rg = bs.solve()
     bs.close()
     assert all(r["status"] == 0 for r in rg)
-    sample = [0, 428, 1000, 2047, 3071, 4095]
-    ref = []
     for i in sample:
-        qp = batch.instance(i)
-        s = orc.OracleSettings(eps=1e-6, norm_A=gA[i], norm_Q=gQ[i])
-        x, y, r, _ = orc.solve(qp, s)
-        ref.append((x, y, r, gA[i], gQ[i]))
-    for (xo, yo, ro, _, _), i in zip(ref, sample):
+        xo, yo, ro = ref[i]
         v0, v1 = batch.var_off[i], batch.var_off[i + 1]
-        r0, r1 = batch.row_off[i], batch.row_off[i + 1]
+        r0_, r1_ = batch.row_off[i], batch.row_off[i + 1]
         g = rg[i]
         print(f"  [{i}] oracle it={ro['iterations']} | gpu it={g['iterations']}", flush=True)
         assert g["iterations"] == ro["iterations"] and g["status"] == ro["status"]
+        assert g["restarts"] == ro["restarts"]
         assert abs(g["rel_kkt"] - ro["rel_kkt"]) <= 1e-8
+        assert abs(g["primal_obj"] - ro["primal_obj"]) <= 1e-8 * (1 + abs(ro["primal_obj"]))
         zo = np.concatenate([xo, yo])
-        zg = np.concatenate([xg[v0:v1], yg[r0:r1]])
+        zg = np.concatenate([xg[v0:v1], yg[r0_:r1_]])
         assert np.max(np.abs(zg - zo)) <= 1e-8 * (1 + np.max(np.abs(zo)))
+
+
+def test_batch_full_size_sampled(orc, qpa):
+    """4096 MPC QPs without preprocessing (autotuned teams)."""
+    _full_batch_sampled(orc, qpa, precondition=False)
+
+
+def test_batch_full_size_preconditioned_sampled(orc, qpa):
+    """4096 MPC QPs exactly as the benchmark times them: Sec. 5 preprocessing on the
+    device, autotuned teams, relKKT 1e-6; the sample includes the slowest instance."""
+    _full_batch_sampled(orc, qpa, precondition=True)
 
 
 def _slice_edge_instance(seed=21, n=200, m=300):

@@ -368,6 +368,38 @@ def test_large_random_full_size(orc, qpa):
     _assert_parity(orc, qp, o, g)
 
 
+@pytest.fixture
+def oracle_threads(orc):
+    """The oracle's threaded mode (bitwise the one-thread result) for full-size legs."""
+    import os
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    yield
+    orc.set_threads(1)
+
+
+def test_large_random_full_size_to_tolerance(orc, qpa, oracle_threads):
+    """The full-size large random QP solved to relKKT 1e-6 (about 2000 iterations, with
+    restarts and primal-weight updates), in the benchmark's launch configuration."""
+    qp = qpgen.large_random_qp()
+    nA, _ = orc.norm_A(qp, 40, 1e-7)
+    nQ, _ = orc.norm_Q(qp, 40, 1e-7)
+    o, g = _pair(orc, qpa, qp, eps=1e-6, norms=(nA, nQ))
+    _assert_parity(orc, qp, o, g)
+    assert o[2]["restarts"] > 3
+
+
+def test_portfolio_full_size_preconditioned(orc, qpa, oracle_threads):
+    """The full factor-model portfolio QP with Sec. 5 preprocessing (the configuration
+    the benchmark solves to tolerance), 1024 iterations through several restarts."""
+    qp = qpgen.portfolio_qp()
+    sc, _, _ = orc.precondition(qp)
+    nA, _ = orc.norm_A(sc, 40, 1e-7)
+    nQ, _ = orc.norm_Q(sc, 40, 1e-7)
+    o, g = _pair(orc, qpa, qp, eps=0.0, max_iter=1024, precondition=True, norms=(nA, nQ))
+    _assert_parity(orc, qp, o, g)
+    assert o[2]["restarts"] > 3
+
+
 def test_portfolio_full_size(orc, qpa):
     """The full factor-model portfolio QP (n = 5e5 + 1000, a 5e5-nonzero budget row)."""
     qp = qpgen.portfolio_qp()
