@@ -626,7 +626,10 @@ static int solve_impl(const orc_problem *p, const orc_problem *orig, const doubl
         kkt_evals += 2;
         double r = kcur.rel_kkt, rb = kavg.rel_kkt;
         int cand_avg;
-        if (fixed) cand_avg = 1;                      /* Alg. 1 returns the average */
+        /* Algorithm 1 and the Sec. 5 methods (fixed-frequency, halving and no restart)
+         * output and are measured at the average; choosing the better of the current
+         * iterate and the average is the Sec. 6 rule (GetRestartCandidate) */
+        if (s->restart_mode != ORC_RESTART_ADAPTIVE) cand_avg = 1;
         else cand_avg = !(r < rb);                    /* Sec. 6 GetRestartCandidate */
         double rc = cand_avg ? rb : r;
         kc = cand_avg ? kavg : kcur;
@@ -653,7 +656,6 @@ static int solve_impl(const orc_problem *p, const orc_problem *orig, const doubl
                 break;
             case ORC_RESTART_HALVING: /* Sec. 5: restart when relKKT(z-bar) <= r0 / 2 */
                 restart = rb <= 0.5 * r0;
-                if (restart) { cand_avg = 1; rc = rb; }
                 break;
             case ORC_RESTART_FIXED_K:
                 restart = 1;

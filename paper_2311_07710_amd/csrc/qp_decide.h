@@ -154,8 +154,11 @@ __device__ __forceinline__ int decide_update(int mode, const double *ra, const d
         S.checks += 1;
         const double r = k0[3], rb = k1[3];
         const bool fixed = s.restart_mode == MODE_FIXED_K;
-        int cand_avg = fixed ? 1 : !(r < rb);   // Sec. 6 GetRestartCandidate (ties: average)
-        double rc = cand_avg ? rb : r;
+        // Algorithm 1 and the Sec. 5 methods (fixed frequency, halving, no restart) are
+        // measured at the average; the better of iterate and average is the Sec. 6 rule
+        // GetRestartCandidate (ties: average)
+        const int cand_avg = s.restart_mode != MODE_ADAPTIVE ? 1 : !(r < rb);
+        const double rc = cand_avg ? rb : r;
         if (isnan(r) || isnan(rb)) {
             S.status = ST_NUMERICAL;
             S.done = 1;
@@ -174,10 +177,6 @@ __device__ __forceinline__ int decide_update(int mode, const double *ra, const d
                       ((double)S.k >= s.beta_artificial * (double)S.total);
         } else if (s.restart_mode == MODE_HALVING) {   // Sec. 5 adaptive restart
             restart = rb <= 0.5 * S.r0;
-            if (restart) {
-                cand_avg = 1;
-                rc = rb;
-            }
         } else if (fixed) {                            // Algorithm 1
             restart = 1;
         }

@@ -24,6 +24,8 @@ from .instances import (  # noqa: F401
     lasso_qp,
     huber_qp,
     svm_qp,
+    ablation_set,
+    ABLATION_CLASSES,
     primal_infeasible_qp,
     dual_infeasible_qp,
     with_contradictory_rows,

@@ -490,6 +490,35 @@ def svm_qp(seed: int = 10, n_features: int = 500, m_samples: int = 5000,
 # ---------------------------------------------------------------------------
 # Infeasible and unbounded variants (inputs for infeasibility detection).
 # ---------------------------------------------------------------------------
+ABLATION_CLASSES = ("random", "eq", "control", "portfolio", "huber", "lasso", "svm")
+
+
+def ablation_set(per_class: int = 24) -> list:
+    """Small instances of the seven synthetic classes of the paper's QP test set (random,
+    equality-constrained, control, portfolio, Huber, Lasso, SVM), `per_class` of each in
+    that class order, with sizes in the tens to hundreds of variables: a synthetic stand-in
+    for a mixed benchmark set, solved by every method of the momentum / restart
+    comparison."""
+    out = []
+    for cls in ABLATION_CLASSES:
+        for k in range(per_class):
+            if cls == "random":
+                out.append(tiny_random_qp(k + 1))
+            elif cls == "eq":
+                out.append(eq_qp(seed=100 + k, n=300))
+            elif cls == "control":
+                out.append(mpc_qp(np.random.default_rng([6, k]), 20 + 5 * (k % 16), 6, 3))
+            elif cls == "portfolio":
+                out.append(portfolio_qp(seed=200 + k, n_assets=400, k=20))
+            elif cls == "huber":
+                out.append(huber_qp(seed=300 + k, n_features=40, m_samples=300))
+            elif cls == "lasso":
+                out.append(lasso_qp(seed=400 + k, n_features=40, m_samples=300))
+            else:
+                out.append(svm_qp(seed=500 + k, n_features=40, m_samples=300))
+    return out
+
+
 def primal_infeasible_qp(seed: int = 1, n: int = 100, m: int = 50) -> QPInstance:
     """The tiny random QP plus two contradictory rows a'x >= 1 and -a'x >= 0 for a dense
     random a: y = (1, 1) on them is a Farkas certificate (A'y = 0, b'y = 1)."""
