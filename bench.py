@@ -247,19 +247,7 @@ def main():
         out["time_to_tolerance"] = tt
 
     if not args.no_cpu:
-        import oracle
-        onA, _ = oracle.norm_A(qp, 40, 1e-7)
-        onQ, _ = oracle.norm_Q(qp, 40, 1e-7)
-        n_it = 448
-        t = time.perf_counter()
-        _, _, ro, _ = oracle.solve(qp, oracle.OracleSettings(eps=0.0, max_iter=n_it, norm_A=onA,
-                                                             norm_Q=onQ))
-        dt = time.perf_counter() - t
-        out["cpu_baseline"] = {"value": ro["iterations"] / dt, "unit": "iters/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"{n_it} rAPDHG iterations (KKT checked every 64) of the "
-                                         "same full-size instance, single-threaded C oracle"}
-        log(f"[bench] cpu oracle {ro['iterations'] / dt:.2f} iters/s ({dt:.1f}s)")
+        out["cpu_baseline"] = cpu_baseline(qp, log)
 
     solver.close()
     if not args.no_batch:
@@ -273,6 +261,42 @@ def main():
     if not args.no_warmstart:
         out["warm_start"] = bench_warmstart(log, args.ws_count)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(qp, log):
+    """The oracle (plain FP64 C, sequential sums in the paper's order) on the host: 1024
+    rAPDHG iterations of the same instance (KKT evaluation every 64) with its threaded mode
+    on the host's CPU share (row ranges split over OpenMP threads; every sum keeps its
+    order, so the result is bitwise the one-thread one), and a one-thread run beside it."""
+    import platform
+    import subprocess
+    import oracle
+    ncpu = os.cpu_count() or 1
+    share = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else ncpu
+    threads = max(1, min(16, share))
+    model = platform.processor() or ""
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    onA, _ = oracle.norm_A(qp, 40, 1e-7)
+    onQ, _ = oracle.norm_Q(qp, 40, 1e-7)
+    rates = {}
+    for th, n_it in ((threads, 1024), (1, 256)):
+        oracle.set_threads(th)
+        t = time.perf_counter()
+        _, _, ro, _ = oracle.solve(qp, oracle.OracleSettings(eps=0.0, max_iter=n_it, norm_A=onA,
+                                                             norm_Q=onQ))
+        rates[th] = ro["iterations"] / (time.perf_counter() - t)
+        log(f"[bench] cpu oracle {th} thread(s): {rates[th]:.2f} iters/s ({n_it} iterations)")
+    oracle.set_threads(1)
+    return {"value": rates[threads], "unit": "iters/s", "cores": threads, "kind": "oracle",
+            "sample": f"1024 rAPDHG iterations (KKT evaluated every 64) of the same full-size "
+                      f"instance, C oracle on {threads} OpenMP threads (sums in fixed order)",
+            "value_1_thread": rates[1], "sample_1_thread": "256 iterations, one thread",
+            "host": {"nproc": ncpu, "cpu_share": share, "model": model}}
 
 
 def bench_batch(log):
@@ -492,6 +516,21 @@ def bench_warmstart(log, count):
     _, _, cold, t_cold = ws.solve_family(fam, te, s6, log=lambda msg: log(f"[bench] cold: {msg}"))
     _, _, warm, t_warm = ws.solve_family(fam, te, s6, x0=x0, y0=y0, omega0=w0,
                                          log=lambda msg: log(f"[bench] warm: {msg}"))
+    # what the network adds over constant priors taken from the training labels: the mean
+    # solution with the geometric-mean primal weight, and the primal weight alone
+    # (predicted, or the training geometric mean) from a zero start
+    nt = te.size
+    gm = np.full(nt, float(np.exp(np.log(omega).mean())))
+    xm, ym = np.tile(X.mean(axis=0), (nt, 1)), np.tile(Y.mean(axis=0), (nt, 1))
+    rows = {}
+    for name, kw in (("mean_solution_start", dict(x0=xm, y0=ym, omega0=gm)),
+                     ("predicted_omega_only", dict(omega0=w0)),
+                     ("mean_omega_only", dict(omega0=gm))):
+        _, _, rs, t_r = ws.solve_family(fam, te, s6, **kw)
+        its = np.array([r["iterations"] for r in rs], dtype=float)
+        rows[name] = {"iterations_mean": its.mean(), "seconds": t_r,
+                      "optimal": int(sum(r["status"] == 0 for r in rs))}
+        log(f"[bench] held-out {name}: {its.mean():.0f} it / {t_r:.2f}s")
     ci = np.array([r["iterations"] for r in cold], dtype=float)
     wi = np.array([r["iterations"] for r in warm], dtype=float)
     kept = int(sum(r["used_warm_start"] for r in warm))
@@ -502,6 +541,7 @@ def bench_warmstart(log, count):
                         f"({ntr} train / {te.size} held out), eps 1e-6",
             "cold_iterations_mean": ci.mean(), "warm_iterations_mean": wi.mean(),
             "cold_seconds": t_cold, "warm_seconds": t_warm, "inference_seconds": pred_s,
+            "constant_priors": rows,
             "warm_kept": kept, "warm_optimal": okw, "held_out": int(te.size),
             "label_solve_seconds": t_lab, "train_seconds": train_s,
             "loss_first_epoch": model.history[0], "loss_last_epoch": model.history[-1],

@@ -5,8 +5,9 @@ library's own forward/backward/Adam kernels; held-out instances are solved to
 relKKT 1e-6 from the predicted point (kept only if its relKKT beats the cold
 start's) and from zeros.  Every warm-started result must meet the same
 termination test as the cold one; the network must predict the held-out
-solutions better than their training mean, cut iterations against the cold start
-and do no worse than the mean solution as a start.
+solutions better than their training mean and cut iterations against the cold
+start; against a constant start (the training-mean solution) its iteration count
+is equal within the measured 5 %.
 """
 import numpy as np
 import pytest
@@ -54,16 +55,24 @@ def test_learned_warm_start_gain(ws):
     xw, yw, warm, t_warm = ws.solve_family(fam, te, Settings(eps=1e-6), x0=x0, y0=y0, omega0=w0)
     xm = np.tile(X.mean(axis=0), (te.size, 1))
     ym = np.tile(Y.mean(axis=0), (te.size, 1))
-    _, _, meanst, _ = ws.solve_family(fam, te, Settings(eps=1e-6), x0=xm, y0=ym,
-                                      omega0=np.full(te.size, np.exp(np.log(omega).mean())))
+    gm = np.full(te.size, np.exp(np.log(omega).mean()))
+    _, _, meanst, _ = ws.solve_family(fam, te, Settings(eps=1e-6), x0=xm, y0=ym, omega0=gm)
+    _, _, wonly, _ = ws.solve_family(fam, te, Settings(eps=1e-6), omega0=w0)
     it = lambda rs: np.array([r["iterations"] for r in rs], dtype=float)  # noqa: E731
     print(f"held-out squared error: learned {err_l:.3e}, mean solution {err_m:.3e} | "
-          f"cold {it(cold).mean():.0f} it ({t_cold:.3f}s) | mean-solution start "
-          f"{it(meanst).mean():.0f} it | learned {it(warm).mean():.0f} it ({t_warm:.3f}s), "
+          f"cold {it(cold).mean():.0f} it ({t_cold:.3f}s) | predicted omega only "
+          f"{it(wonly).mean():.0f} it | mean-solution start {it(meanst).mean():.0f} it | "
+          f"learned {it(warm).mean():.0f} it ({t_warm:.3f}s), "
           f"kept {sum(r['used_warm_start'] for r in warm)}/{te.size}", flush=True)
-    assert all(r["status"] == 0 and r["rel_kkt"] <= 1e-6 for r in warm + cold)
+    assert all(r["status"] == 0 and r["rel_kkt"] <= 1e-6 for r in warm + cold + meanst + wonly)
+    # the network predicts the held-out solutions better than their training mean does
     assert err_l < 0.8 * err_m
+    # against the method without it (cold start): the predicted point and weight cut the
+    # iterations; the predicted weight alone does most of it
     assert it(warm).mean() < 0.8 * it(cold).mean()
-    # the remaining iterations are spent on the last digits (linear convergence), so a
-    # better start gains little over the mean one; it must not be worse
-    assert it(warm).mean() <= 1.05 * it(meanst).mean()
+    assert it(wonly).mean() < 0.8 * it(cold).mean()
+    # Measured comparison with a constant prior (training-mean solution, geometric-mean
+    # weight): on this family learned 780 vs mean 774 iterations, on the 5000-asset
+    # family 3447 vs 3474; the last digits of a linearly converging method dominate, and a
+    # better start shortens only the first phase.  Asserted: equal within 5 %.
+    assert abs(it(warm).mean() - it(meanst).mean()) <= 0.05 * it(meanst).mean()
