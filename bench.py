@@ -309,39 +309,90 @@ def bench_batch(log):
     batch = qpgen.mpc_batch(seed=4, count=4096)
     log(f"[bench] MPC batch generated in {time.time() - t:.1f}s "
         f"(sum n={batch.var_off[-1]}, sum m={batch.row_off[-1]})")
-    t = time.time()
-    bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6, precondition=1))
-    create_s = time.time() - t
+    import torch
+    n_i = np.diff(batch.var_off)
+    m_i = np.diff(batch.row_off)
+    a_nnz = np.diff(batch.a_rowptr[batch.row_off].astype(np.int64))
+    q_nnz = np.diff(batch.q_rowptr[batch.var_off].astype(np.int64))
+    # bytes one iteration of instance i reads from memory beyond its team's LDS: the rows
+    # of A and of P = [Q | -A'] (8 B value + 4 B column per nonzero, 4 B row pointers), and
+    # c, l, u (24 B per variable), b and the row type (9 B per row); the iterates live in LDS
+    it_bytes = 12.0 * (2 * a_nnz + q_nnz) + 4.0 * (n_i + m_i + 2) + 24.0 * n_i + 9.0 * m_i
+    # memory-side ceiling for this access pattern: a device copy of a buffer that the L2s
+    # and the 256 MB MALL hold (64 MiB read + 64 MiB written, repeated)
+    src = torch.ones(8 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
     t = time.perf_counter()
-    threads = bs.autotune(sample=128, iters=256)
-    tune_s = time.perf_counter() - t
-    t = time.perf_counter()
-    _, _, res = bs.solve()
-    dt = time.perf_counter() - t
-    its = np.array([r["iterations"] for r in res])
-    ok = int(sum(r["status"] == 0 for r in res))
-    gA, gQ = bs.norms()
-    bs.close()
-    log(f"[bench] batched: {batch.count} instances in {dt:.3f}s ({batch.count / dt:.0f}/s), "
-        f"{ok} optimal, threads {threads}")
+    for _ in range(50):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    mall_gbs = 50 * 2 * src.numel() * 8 / (time.perf_counter() - t) / 1e9
+    del src, dst
+    out = {"workload": "4096 MPC QPs, T~U{10..100}, n_x~U{4..12}, n_u~U{2..4}, FP64, eps 1e-6"}
+    for pre in (1, 0):
+        t = time.time()
+        bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6, precondition=pre))
+        create_s = time.time() - t
+        t = time.perf_counter()
+        threads = bs.autotune(sample=128, iters=256)
+        tune_s = time.perf_counter() - t
+        t = time.perf_counter()
+        _, _, res = bs.solve()
+        dt = time.perf_counter() - t
+        its = np.array([r["iterations"] for r in res], dtype=float)
+        end = np.array([r["end_s"] for r in res])
+        start = np.array([r["start_s"] for r in res])
+        ok = int(sum(r["status"] == 0 for r in res))
+        if pre:
+            gA, gQ = bs.norms()
+        bs.close()
+        slow = int(np.argmax(its))
+        moved = float(np.sum(its * it_bytes))
+        row = {"instances_per_s": batch.count / dt, "seconds": dt, "optimal": ok,
+               "iterations_mean": float(its.mean()), "iterations_max": int(its.max()),
+               "completion_s": {"p50": float(np.percentile(end, 50)),
+                                "p99": float(np.percentile(end, 99)), "max": float(end.max())},
+               "slowest": {"instance": slow, "iterations": int(its[slow]),
+                           "n_plus_m": int(n_i[slow] + m_i[slow]), "start_s": float(start[slow]),
+                           "end_s": float(end[slow]),
+                           "us_per_iteration": 1e6 * float(end[slow] - start[slow]) / its[slow]},
+               "threads_per_class": threads, "autotune_s": tune_s, "create_s": create_s,
+               "memory_bytes_moved": moved, "GBps": moved / dt / 1e9}
+        key = "preprocessed" if pre else "not_preprocessed"
+        out[key] = row
+        log(f"[bench] batched ({key}): {batch.count} instances in {dt:.3f}s "
+            f"({batch.count / dt:.0f}/s), {ok} optimal, threads {threads}; completion p50 "
+            f"{row['completion_s']['p50']:.3f}s p99 {row['completion_s']['p99']:.3f}s max "
+            f"{row['completion_s']['max']:.3f}s; slowest instance {slow}: {int(its[slow])} "
+            f"iterations from {start[slow]:.3f}s to {end[slow]:.3f}s; "
+            f"{row['GBps']:.0f} GB/s of matrix and data streams")
+    pre = out["preprocessed"]
     sample = list(range(0, batch.count, 256))
     t = time.perf_counter()
-    single_its = 0
     for i in sample:
         with qpa.Solver(batch.instance(i), qpa.Settings(eps=1e-6, norm_A=gA[i], norm_Q=gQ[i],
                                                          precondition=1)) as s:
-            _, _, r = s.solve()
-            single_its += r["iterations"]
+            s.solve()
     st = time.perf_counter() - t
     log(f"[bench] looping qp_solve over {len(sample)} instances: {st:.2f}s "
         f"({len(sample) / st:.1f}/s)")
-    return {"workload": "4096 MPC QPs, T~U{10..100}, n_x~U{4..12}, n_u~U{2..4}, FP64, eps 1e-6, "
-                        "Sec. 5 preprocessing",
-            "instances_per_s": batch.count / dt, "seconds": dt, "optimal": ok,
-            "iterations_mean": float(its.mean()), "iterations_max": int(its.max()),
-            "threads_per_class": threads, "autotune_s": tune_s, "create_s": create_s,
-            "single_loop_instances_per_s": len(sample) / st, "single_loop_sample": len(sample),
-            "speedup_vs_single_loop": (batch.count / dt) / (len(sample) / st)}
+    out.update({"instances_per_s": pre["instances_per_s"], "seconds": pre["seconds"],
+                "single_loop_instances_per_s": len(sample) / st,
+                "single_loop_sample": len(sample),
+                "speedup_vs_single_loop": pre["instances_per_s"] / (len(sample) / st),
+                "roofline": {"bound": "latency",
+                             "note": "each instance's iteration is a chain of dependent loads "
+                                     "and barriers on one workgroup; the makespan is the "
+                                     "slowest instance's iterations times its per-iteration "
+                                     "latency",
+                             "achieved": pre["GBps"], "peak": mall_gbs, "unit": "GB/s",
+                             "peak_kind": "measured device copy of a 64 MiB buffer (L2/MALL "
+                                          "resident), read + write",
+                             "frac": pre["GBps"] / mall_gbs}})
+    return out
 
 
 def bench_ablation(log):

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define QP_ABI_VERSION 1
+#define QP_ABI_VERSION 2
 
 /* return codes */
 #define QP_OK 0
@@ -200,7 +200,10 @@ typedef struct {
     double primal_obj, dual_obj;
     double omega;            /* final primal weight */
     double norm_A, norm_Q;   /* operator norms used */
-    double solve_time_s;     /* host wall time of the solve */
+    double solve_time_s;     /* host wall time of the solve (a batch: of the whole batch) */
+    double start_s, end_s;   /* batch: when this instance's solve started and ended on the
+                                device, in seconds after the batch began (device wall
+                                clock); single solve: 0 and solve_time_s */
 } qp_result;
 
 typedef struct {

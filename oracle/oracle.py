@@ -12,7 +12,9 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB names another build of the same source (the sanitizer test builds one with
+# AddressSanitizer and UndefinedBehaviorSanitizer and runs the oracle's tests against it)
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 RESTART_ADAPTIVE, RESTART_FIXED_K, RESTART_HALVING, RESTART_NONE = 0, 1, 2, 3
 OPTIMAL, ITERATION_LIMIT, TIME_LIMIT, NUMERICAL_ERROR = 0, 1, 2, 3

@@ -72,7 +72,8 @@ class qp_result(C.Structure):
                 ("restarts", C.c_int64), ("kkt_evals", C.c_int64), ("rel_kkt", C.c_double),
                 ("r_primal", C.c_double), ("r_dual", C.c_double), ("r_gap", C.c_double),
                 ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("omega", C.c_double),
-                ("norm_A", C.c_double), ("norm_Q", C.c_double), ("solve_time_s", C.c_double)]
+                ("norm_A", C.c_double), ("norm_Q", C.c_double), ("solve_time_s", C.c_double),
+                ("start_s", C.c_double), ("end_s", C.c_double)]
 
 
 class qp_profile(C.Structure):
@@ -120,6 +121,7 @@ MLP_SIGNATURES = {
 }
 
 _lib = None
+ABI_VERSION = 2  # QP_ABI_VERSION of include/qp.h (qp_result gained start_s, end_s)
 
 
 def load():
@@ -134,6 +136,9 @@ def load():
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
+        if lib.qp_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {lib.qp_version()}, this binding "
+                               f"expects {ABI_VERSION}: rebuild the library")
         _lib = lib
     return _lib
 

@@ -989,6 +989,8 @@ void fill_result(const qp_handle *h, const State &S, double t, qp_result *res) {
     res->norm_A = h->norm_A;
     res->norm_Q = h->norm_Q;
     res->solve_time_s = t;
+    res->start_s = 0.0;
+    res->end_s = t;
 }
 
 }  // namespace

@@ -534,6 +534,7 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
             S.restart_flag = 0;
             S.used_warm = (warm && !pair) ? 1 : 0;
             S.checks = 0;
+            S.t_start = (int64_t)wall_clock64() - *a.clock0;
         }
         __syncthreads();
         double ra[RA_NV], rp[RP_NV];
@@ -721,7 +722,10 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
         const int avg = S.cand;
         for (int j = t; j < n; j += NT) a.x_out[v0 + j] = avg ? xbar[j] : x[j];
         for (int i = t; i < m; i += NT) a.y_out[r0 + i] = avg ? ybar[i] : y[i];
-        if (t == 0) a.res[id] = S;
+        if (t == 0) {
+            S.t_end = (int64_t)wall_clock64() - *a.clock0;
+            a.res[id] = S;
+        }
     }
 }
 
@@ -1762,6 +1766,8 @@ int batch_solve(BatchData *bd, const qp_settings *s, int ms, const qp_warm_start
         r.norm_A = bd->normA[i];
         r.norm_Q = bd->normQ[i];
         r.solve_time_s = dt;
+        r.start_s = (double)Z.t_start / (1000.0 * (double)bd->wall_khz);
+        r.end_s = (double)Z.t_end / (1000.0 * (double)bd->wall_khz);
     }
     return QP_OK;
 }

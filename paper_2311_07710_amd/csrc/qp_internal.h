@@ -108,6 +108,7 @@ struct State {
     int64_t total, k, restarts, kkt_evals;
     int32_t done, status, cand, restart_flag;
     int32_t used_warm, checks, pad0, pad1;
+    int64_t t_start, t_end;  // batch: device wall-clock ticks after the launch began
 };
 
 struct DevSettings {

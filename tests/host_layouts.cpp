@@ -1,6 +1,8 @@
-// Host-side layout builders of qp_create checked against their definitions: the
-// row-threaded P = [Q | -A'] build and the column-panel split.  Built by
-// tests/test_host_layouts.py with hipcc against the library; no GPU call is made.
+// Host-side code of qp_create checked without a GPU: input validation (invalid host
+// problems are rejected before any device call), and the layout builders against their
+// definitions: the row-threaded P = [Q | -A'] build and the column-panel split.  Built by
+// tests/test_host_layouts.py with hipcc against the library, plainly and with host-side
+// AddressSanitizer and UndefinedBehaviorSanitizer; no GPU call is made.
 #include "../paper_2311_07710_amd/csrc/qp_api.cpp"
 
 #include <random>
@@ -102,8 +104,62 @@ static int check_panels(std::mt19937_64 &g) {
     return 0;
 }
 
+// qp_create on host input that fails validation: every case is rejected with
+// QP_ERR_INVALID_ARGUMENT before any device call (so this runs without a GPU), and the
+// validation reads no array beyond what the descriptor promises
+static int check_validation() {
+    const int32_t qr[4] = {0, 1, 2, 3}, qc[3] = {0, 1, 2};
+    const double qv[3] = {1.0, 2.0, 3.0};
+    const int32_t ar[3] = {0, 2, 3}, ac[3] = {0, 2, 1};
+    const double av[3] = {1.0, -1.0, 0.5}, c[3] = {1, 2, 3}, b[2] = {0, 1};
+    const uint8_t rt[2] = {0, 1};
+    auto base = [&]() {
+        qp_problem_desc d;
+        std::memset(&d, 0, sizeof(d));
+        d.n = 3;
+        d.m = 2;
+        d.num_instances = 1;
+        d.mem_space = QP_MEM_HOST;
+        d.Q.row_ptr = qr; d.Q.col_idx = qc; d.Q.val = qv; d.Q.nnz = 3;
+        d.A.row_ptr = ar; d.A.col_idx = ac; d.A.val = av; d.A.nnz = 3;
+        d.c = c; d.b = b; d.row_type = rt;
+        return d;
+    };
+    const int32_t qr_desc[4] = {0, 2, 1, 3}, ac_bad[3] = {0, 3, 1}, ar_bad[3] = {1, 2, 3};
+    const uint8_t rt_bad[2] = {0, 7};
+    struct Case { const char *name; void (*edit)(qp_problem_desc &, const void *); const void *arg; };
+    int bad = 0, ncase = 0;
+    auto expect = [&](const char *name, qp_problem_desc d) {
+        qp_handle *h = nullptr;
+        const int rc = qp_create(&d, nullptr, &h);
+        ++ncase;
+        if (rc != QP_ERR_INVALID_ARGUMENT || h) {
+            printf("validation: %s returned %d\n", name, rc);
+            ++bad;
+        }
+    };
+    { auto d = base(); d.n = 0; expect("n = 0", d); }
+    { auto d = base(); d.m = -1; expect("m < 0", d); }
+    { auto d = base(); d.Q.row_ptr = qr_desc; expect("Q row_ptr decreasing", d); }
+    { auto d = base(); d.Q.nnz = 2; expect("Q nnz mismatch", d); }
+    { auto d = base(); d.A.col_idx = ac_bad; expect("A column out of range", d); }
+    { auto d = base(); d.A.row_ptr = ar_bad; expect("A row_ptr[0] != 0", d); }
+    { auto d = base(); d.A.col_idx = nullptr; expect("A col_idx null", d); }
+    { auto d = base(); d.A.val = nullptr; expect("A val null", d); }
+    { auto d = base(); d.Q.val = nullptr; expect("Q val null", d); }
+    { auto d = base(); d.c = nullptr; expect("c null", d); }
+    { auto d = base(); d.b = nullptr; expect("b null", d); }
+    { auto d = base(); d.row_type = rt_bad; expect("row type 7", d); }
+    { auto d = base(); d.mem_space = 9; expect("mem_space", d); }
+    { auto d = base(); d.n = (int64_t)1 << 31; expect("n beyond int32", d); }
+    (void)sizeof(Case);
+    printf("validation: %d cases rejected%s\n", ncase, bad ? " (FAILURES)" : "");
+    return bad ? 1 : 0;
+}
+
 int main() {
     std::mt19937_64 g(11);
+    if (check_validation()) return 1;
     if (check_build_p(g) || check_panels(g)) return 1;
     printf("all ok\n");
     return 0;

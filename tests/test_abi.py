@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
     assert set(mlp_names) == set(B.MLP_SIGNATURES)
     for n in mlp_names:
         assert hasattr(lib, n), n
-    assert lib.qp_version() == 1
+    assert lib.qp_version() == B.ABI_VERSION == 2
 
 
 def test_struct_layouts_match_header(tmp_path):
