@@ -1252,6 +1252,8 @@ __device__ __forceinline__ void load_cols(const int32_t *__restrict__ col, int e
     }
 }
 
+// values of entries e0 + i*BS + t; lanes past e1 read entry e0 (their products are
+// masked where they are formed, so no loaded value is consumed before its use)
 template <int SRC>
 __device__ __forceinline__ void load_vals(const double *__restrict__ val, int e0, int e1, int t,
                                           double (&vals)[EPT]) {
@@ -1259,18 +1261,23 @@ __device__ __forceinline__ void load_vals(const double *__restrict__ val, int e0
     for (int i = 0; i < EPT; ++i) {
         const int e = e0 + i * BS + t;
         const int ee = e < e1 ? e : e0;
-        const double v = SRC == STREAM_P ? __builtin_nontemporal_load(&val[ee]) : val[ee];
-        vals[i] = e < e1 ? v : 0.0;
+        vals[i] = SRC == STREAM_P ? __builtin_nontemporal_load(&val[ee]) : val[ee];
     }
 }
 
-__device__ __forceinline__ int next_slot(const Panels &pn, int idx, int nwg) {
-    while (idx < pn.grid && pn.map[idx] < 0) idx += nwg;
+// The block map and descriptors are read-only during the launch and passed as restrict
+// kernel arguments, so the compiler reads them with scalar loads: waiting for them does
+// not wait for the vector loads (gathers, stream) in flight.
+__device__ __forceinline__ int next_slot(const int32_t *__restrict__ map, int grid, int idx,
+                                         int nwg) {
+    while (idx < grid && map[idx] < 0) idx += nwg;
     return idx;
 }
 
 template <int PHASE>
-__global__ __launch_bounds__(BS) void k_panel_spmv(Panels pn, const double *__restrict__ v1,
+__global__ __launch_bounds__(BS) void k_panel_spmv(Panels pn, const int32_t *__restrict__ map,
+                                                   const PBlock *__restrict__ blk,
+                                                   const double *__restrict__ v1,
                                                    const double *__restrict__ v2, int32_t split,
                                                    int32_t nwg, const State *__restrict__ st) {
     if (st->done) return;
@@ -1278,19 +1285,20 @@ __global__ __launch_bounds__(BS) void k_panel_spmv(Panels pn, const double *__re
     __shared__ double prod[NNZ_BLK];
     __shared__ double scratch[BS / 64];
     const int t = threadIdx.x;
-    int idx = next_slot(pn, blockIdx.x, nwg);
-    if (idx >= pn.grid) return;
-    int bi = pn.map[idx];
-    PBlock B = pn.blk[bi];
+    const int grid = pn.grid;
+    int idx = next_slot(map, grid, blockIdx.x, nwg);
+    if (idx >= grid) return;
+    int bi = map[idx];
+    PBlock B = blk[bi];
     int cols[EPT];
     load_cols<SRC>(pn.col, B.e0, B.e1, t, cols);
     while (true) {
         // next block's descriptor first: its loads complete together with this block's
         // column indices, which the gathers need anyway
-        const int nidx = next_slot(pn, idx + nwg, nwg);
-        const bool more = nidx < pn.grid;
-        const int nbi = more ? pn.map[nidx] : bi;
-        const PBlock NB = pn.blk[nbi];
+        const int nidx = next_slot(map, grid, idx + nwg, nwg);
+        const bool more = nidx < grid;
+        const int nbi = more ? map[nidx] : bi;
+        const PBlock NB = blk[nbi];
         __builtin_amdgcn_sched_barrier(0);
         double g[EPT];
 #pragma unroll
@@ -1308,7 +1316,8 @@ __global__ __launch_bounds__(BS) void k_panel_spmv(Panels pn, const double *__re
         load_cols<SRC>(pn.col, NB.e0, more ? NB.e1 : NB.e0, t, ncols);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) prod[i * BS + t] = vals[i] * g[i];
+        for (int i = 0; i < EPT; ++i)
+            prod[i * BS + t] = B.e0 + i * BS + t < B.e1 ? vals[i] * g[i] : 0.0;
         __syncthreads();
         const int32_t *rp = pn.rowptr + (size_t)B.panel * (size_t)(pn.R + 1);
         double *out = pn.part + (size_t)B.panel * (size_t)pn.R;
@@ -1591,8 +1600,8 @@ void launch_dual_panels(hipStream_t s, const Panels &pn, const Vecs &v, int64_t 
     if (pn.R == 0) return;
     if (pn.grid > 0)
         hipLaunchKernelGGL(k_panel_spmv<0>, dim3(panel_workgroups(pn)), dim3(BS), 0, s, pn,
-                           (const double *)v.xt, (const double *)nullptr, (int32_t)n,
-                           panel_workgroups(pn), st);
+                           pn.map, pn.blk, (const double *)v.xt, (const double *)nullptr,
+                           (int32_t)n, panel_workgroups(pn), st);
     hipLaunchKernelGGL(k_dual_combine, dim3((unsigned)((pn.R + 255) / 256)), dim3(256), 0, s,
                        (const double *)pn.part, pn.np, pn.R, v.y, v.ybar, v.b, v.rt, step, st);
 }
@@ -1602,8 +1611,8 @@ void launch_primal_panels(hipStream_t s, const Panels &pn, const Vecs &v, int md
     const PrimalArgs a = primal_args(v, md_in);
     if (pn.grid > 0)
         hipLaunchKernelGGL(k_panel_spmv<1>, dim3(panel_workgroups(pn)), dim3(BS), 0, s, pn,
-                           (const double *)v.xmd[md_in], (const double *)v.y, (int32_t)n,
-                           panel_workgroups(pn), st);
+                           pn.map, pn.blk, (const double *)v.xmd[md_in], (const double *)v.y,
+                           (int32_t)n, panel_workgroups(pn), st);
     hipLaunchKernelGGL(k_primal_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        (const double *)pn.part, pn.np, n, a, step, st);
 }
