@@ -217,26 +217,40 @@ typedef struct qp_handle qp_handle;
 /* Fills *s with the defaults listed above. */
 void qp_default_settings(qp_settings *s);
 
-/* Validates the problem, copies it into library-owned device memory (the caller
+/* Sets up the problem of Sec. 1 eq. (qp) (generalised as above) for rAPDHG.
+ * Validates the problem, copies it into library-owned device memory (the caller
  * keeps ownership of its arrays and may free them after the call), builds the
  * device layouts (A, and [Q | -A'] as one CSR matrix) and estimates ||A||_2 and
- * ||Q||_2 by power iteration unless settings->norm_A / norm_Q > 0.  settings may
- * be NULL (defaults).  On success *out receives a handle to free with qp_free.
+ * ||Q||_2 -- the operator norms the Sec. 6 step-size rule and Theorem 1's fixed-K
+ * steps need -- by power iteration unless settings->norm_A / norm_Q > 0.  With
+ * settings->precondition = 1 it applies the Sec. 5 diagonal preprocessing first.
+ * settings may be NULL (defaults).  On success *out receives a handle to free with
+ * qp_free.
  * Errors: QP_ERR_INVALID_ARGUMENT (malformed CSR, l > u, bad row type, index
  * overflow, both ||A|| and ||Q|| zero), QP_ERR_OUT_OF_MEMORY, QP_ERR_DEVICE. */
 int qp_create(const qp_problem_desc *desc, const qp_settings *settings, qp_handle **out);
 
-/* Solves a single QP (num_instances == 1) from zeros or from ws (nullable).
- * x_out [n] and y_out [m] receive the returned point (the restart candidate at the
- * final evaluation); they live in the handle's mem_space and may be NULL.
- * Returns QP_ERR_BATCH_MISMATCH for a batch handle. */
+/* Solves a single QP (num_instances == 1) from zeros or from ws (nullable): the inner
+ * loop of Algorithm 1 (accelerated PDHG with momentum averaging), restarted and stepped
+ * by the Sec. 6 rules (adaptive restart criteria, step-size rule, primal weight) or, by
+ * settings, by Algorithm 1's fixed frequency or the Sec. 5 halving rule, until the
+ * Sec. 5 relative KKT error of the returned point is at most settings->eps.
+ * x_out [n] and y_out [m] receive the returned point (Sec. 6 rule: the restart
+ * candidate of the final evaluation; the Sec. 5 modes and fixed frequency: the
+ * average); they live in the handle's mem_space and may be NULL.  Blocking with respect
+ * to the handle's stream.  Returns QP_ERR_BATCH_MISMATCH for a batch handle; a solve
+ * that does not converge returns QP_OK with res->status set. */
 int qp_solve(qp_handle *h, const qp_warm_start *ws, qp_result *res, double *x_out,
              double *y_out);
 
-/* Solves every instance of a batch handle in one persistent kernel launch.
+/* Solves every instance of a batch handle (the same method as qp_solve: Algorithm 1 with
+ * the Sec. 6 or Sec. 5 restart rules and the Sec. 5 termination test, applied to each
+ * instance independently) in one persistent kernel launch per size class.
  * ws_array: NULL or B warm starts whose x0/y0 point into instance-local arrays;
  * res_array: B results; x_out/y_out: concatenated by var_off / row_off (nullable).
- * Every instance runs the same algorithm and settings as qp_solve. */
+ * Every instance runs the same algorithm and settings as qp_solve and returns the
+ * result qp_solve would return for it alone with the same norms.  Blocking.  Returns
+ * QP_ERR_BATCH_MISMATCH for a single-QP handle. */
 int qp_batch_solve(qp_handle *h, const qp_warm_start *ws_array, qp_result *res_array,
                    double *x_out, double *y_out);
 

@@ -121,7 +121,7 @@ def test_tiny_config_to_tolerance(orc, qpa):
     assert g[2]["status"] == 0 and g[2]["rel_kkt"] <= 1e-6
 
 
-@pytest.mark.parametrize("seed", list(range(1001, 1021)))
+@pytest.mark.parametrize("seed", list(range(1001, 1101)))
 def test_tiny_config_seed_sweep(orc, qpa, seed):
     qp = qpgen.tiny_random_qp(seed)
     o, g = _pair(orc, qpa, qp, eps=1e-6)
