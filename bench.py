@@ -31,6 +31,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rAPDHG iters/s + time-to-1e-6 KKT; SpMV HBM GB/s % peak; warm vs cold"
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+# random FP64 gathers per second from a vector slice held in one XCD's L2, measured with a
+# standalone probe kernel (column index + value streamed, one gather per entry)
+GATHER_CEILING = 210e9
 
 
 PROFILE_MD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -200,13 +203,19 @@ def main():
         p_avg = primal_ms / primal_n
         p_gbs = primal_bytes / (p_avg * 1e-3) / 1e9
         d_gbs = dual_bytes / (d_avg * 1e-3) / 1e9
+        # the phase's random FP64 gathers (one per nonzero of P) against the rate measured
+        # for gathers that stay in one XCD's L2 (a standalone probe, 210 G/s)
+        gathers_ps = (qp.q_nnz + qp.a_nnz) / (p_avg * 1e-3)
         out["roofline"] = {"bound": "hbm",
                            "kernel": "primal phase (k_panel_spmv<1> + k_primal_combine)",
                            "achieved": p_gbs,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": p_gbs / HBM_PEAK_GBS,
                            "traffic": measured_traffic(), "avg_us": 1000.0 * p_avg,
                            "algorithmic_bytes_per_launch": primal_bytes,
-                           "copy_GBps": copy_gbs, "frac_of_copy": p_gbs / copy_gbs}
+                           "copy_GBps": copy_gbs, "frac_of_copy": p_gbs / copy_gbs,
+                           "gathers_per_s": gathers_ps,
+                           "gather_ceiling_per_s": GATHER_CEILING,
+                           "frac_of_gather_ceiling": gathers_ps / GATHER_CEILING}
         out["kernels"] = {
             "k_dual": {"avg_us": 1000.0 * d_avg, "bytes": dual_bytes, "GB/s": d_gbs,
                        "frac": d_gbs / HBM_PEAK_GBS, "launches": dual_n},
