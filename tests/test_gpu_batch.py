@@ -304,3 +304,39 @@ def test_batch_instance_too_large_for_lds(orc, qpa):
         xg, yg, rg = bs.solve()
         bs.close()
         _compare(batch, xg, yg, rg, ref)
+
+
+@pytest.mark.parametrize("mom,mode,K", [(1, 2, 100), (0, 2, 100), (1, 3, 100), (0, 3, 100),
+                                        (1, 1, 10)])
+def test_batch_ablation_modes_preconditioned(orc, qpa, mom, mode, K):
+    """The configuration of the Sec. 5 comparison in the benchmark: preprocessing on, each
+    method as a batched launch over instances of the seven synthetic classes (two each),
+    checked per instance against the oracle's solve of its own scaling of the instance
+    (the no-restart methods stop at the iteration limit)."""
+    per = 2
+    insts = [q for k, q in enumerate(qpgen.ablation_set(24)) if k % 24 < per]
+    batch = qpgen.concat_batch(insts)
+    cap = 6000
+    refs = []
+    for qp in insts:
+        sc, dv, dr = orc.precondition(qp)
+        nA, _ = orc.norm_A(sc, 1000, 1e-7)
+        nQ, _ = orc.norm_Q(sc, 1000, 1e-7)
+        s = orc.OracleSettings(eps=1e-6, max_iter=cap, momentum=mom, restart_mode=mode,
+                               fixed_K=K, norm_A=nA, norm_Q=nQ)
+        refs.append((*orc.solve_scaled(sc, qp, dv, dr, s)[:3], nA, nQ))
+    bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6, max_iter=cap, momentum=mom,
+                                             restart_mode=mode, fixed_K=K, precondition=1))
+    bs.set_norms([r[3] for r in refs], [r[4] for r in refs])
+    xg, yg, rg = bs.solve()
+    bs.close()
+    for i, (xo, yo, ro, _, _) in enumerate(refs):
+        v0, v1 = batch.var_off[i], batch.var_off[i + 1]
+        r0, r1 = batch.row_off[i], batch.row_off[i + 1]
+        g = rg[i]
+        assert g["status"] == ro["status"] and g["iterations"] == ro["iterations"], (i, g, ro)
+        assert g["restarts"] == ro["restarts"]
+        assert abs(g["rel_kkt"] - ro["rel_kkt"]) <= 1e-8
+        zo = np.concatenate([xo, yo])
+        zg = np.concatenate([xg[v0:v1], yg[r0:r1]])
+        assert np.max(np.abs(zg - zo)) <= 1e-8 * (1 + np.max(np.abs(zo)))
