@@ -755,3 +755,93 @@ def test_momentum_and_restart_cut_iterations(orc):
                          for seed in range(1, 9)])
     assert its["rAPDHG"] < its["rPDHG"] < its["PDHG"]
     assert its["rAPDHG-halving"] < its["rPDHG-halving"] < its["PDHG"]
+
+
+# ---------------------------------------------------------------------------
+# Sec. 4 smoothed duality gap (Fercoq's definition as the paper states it) in the
+# paper's form min 1/2 x'Qx + c'x s.t. A_p x <= b_p, Z = R^n x R^m_+.  The closed form
+# eq. (gap-explicit) and the split of lem. (pd=p-d) are checked against a generic
+# numerical maximisation of the definition; the gap is zero exactly at a saddle point,
+# which the oracle's solution must be.
+# ---------------------------------------------------------------------------
+def _paper_form(qp):
+    """GE rows A x >= b are the paper's rows with A_p = -A, b_p = -b (same y >= 0)."""
+    Q, A = qp.dense()
+    return Q, -A, qp.c, -qp.b
+
+
+def _gap_by_maximisation(Q, Ap, c, bp, x, y, xs, ys, xi):
+    """max over (xh, yh >= 0) of L(x,yh) - L(xh,y) - xi/2 ||(xh,yh) - (xs,ys)||^2 with
+    L(x,y) = 1/2 x'Qx + c'x + y'(A_p x - b_p), by bounded quasi-Newton iterations."""
+    from scipy.optimize import minimize
+    n, m = x.size, y.size
+    Lx = lambda xx, yy: 0.5 * xx @ Q @ xx + c @ xx + yy @ (Ap @ xx - bp)  # noqa: E731
+
+    def f(z):
+        xh, yh = z[:n], z[n:]
+        val = Lx(x, yh) - Lx(xh, y) - 0.5 * xi * (np.sum((xh - xs) ** 2) + np.sum((yh - ys) ** 2))
+        gx = -(Q @ xh + c + Ap.T @ y) - xi * (xh - xs)
+        gy = (Ap @ x - bp) - xi * (yh - ys)
+        return -val, -np.concatenate([gx, gy])
+
+    z0 = np.concatenate([xs, np.maximum(ys, 0.0)])
+    r = minimize(f, z0, jac=True, method="L-BFGS-B",
+                 bounds=[(None, None)] * n + [(0.0, None)] * m,
+                 options={"ftol": 1e-16, "gtol": 1e-13, "maxiter": 20000})
+    return -r.fun
+
+
+def _gap_closed_form(Q, Ap, c, bp, x, y, xs, ys, xi):
+    """eq. (gap-explicit), y >= 0 (the indicator term is zero)."""
+    Minv = np.linalg.inv(np.eye(Q.shape[0]) + Q / xi)
+    v = xs - (c + Ap.T @ y) / xi
+    w = np.maximum(ys + (Ap @ x - bp) / xi, 0.0)
+    return (0.5 * x @ Q @ x + c @ x + bp @ y + 0.5 * xi * (w @ w) - 0.5 * xi * (ys @ ys)
+            + 0.5 * xi * (v @ Minv @ v) - 0.5 * xi * (xs @ xs))
+
+
+def _gap_primal_part(Q, Ap, c, bp, x, xs, ys, xi):
+    """lem. (pd=p-d) (ii): the gap at (x, y*)."""
+    r = Ap @ x - bp
+    w = np.maximum(ys + r / xi, 0.0)
+    d = x - xs
+    return 0.5 * xi * (w @ w) - 0.5 * xi * (ys @ ys) - ys @ r + 0.5 * d @ Q @ d
+
+
+def _gap_dual_part(Q, Ap, c, bp, y, xs, xi):
+    """lem. (pd=p-d) (iii): the gap at (x*, y), y >= 0."""
+    Minv = np.linalg.inv(np.eye(Q.shape[0]) + Q / xi)
+    g = Q @ xs + c + Ap.T @ y
+    return g @ Minv @ g / (2 * xi) + y @ (bp - Ap @ xs)
+
+
+@pytest.mark.parametrize("seed", [3, 11])
+def test_smoothed_gap_closed_form_split_and_oracle_saddle(orc, seed):
+    qp = qp_refs.random_tiny_qp(seed, n=6, m=4, bounded_frac=0.0, eq_frac=0.0)
+    Q, Ap, c, bp = _paper_form(qp)
+    _, xs, ys = qp_refs.brute_force_kkt(qp)
+    rng = np.random.default_rng(seed)
+    for xi in (0.5, 2.0, 10.0):
+        for _ in range(3):
+            x = xs + rng.standard_normal(6)
+            y = np.abs(ys + rng.standard_normal(4))
+            g_max = _gap_by_maximisation(Q, Ap, c, bp, x, y, xs, ys, xi)
+            g_cf = _gap_closed_form(Q, Ap, c, bp, x, y, xs, ys, xi)
+            assert g_cf == pytest.approx(g_max, rel=1e-8, abs=1e-9)
+            gp = _gap_primal_part(Q, Ap, c, bp, x, xs, ys, xi)
+            gd = _gap_dual_part(Q, Ap, c, bp, y, xs, xi)
+            assert gp == pytest.approx(_gap_by_maximisation(Q, Ap, c, bp, x, ys, xs, ys, xi),
+                                       rel=1e-8, abs=1e-9)
+            assert gd == pytest.approx(_gap_by_maximisation(Q, Ap, c, bp, xs, y, xs, ys, xi),
+                                       rel=1e-8, abs=1e-9)
+            assert gp + gd == pytest.approx(g_cf, rel=1e-10, abs=1e-10)
+            assert g_cf > 1e-6  # a point off the saddle has a positive gap
+    # the oracle's solution is a saddle point: its smoothed gap centred at itself vanishes
+    xo, yo, r, _ = orc.solve(qp, orc.OracleSettings(eps=1e-12, max_iter=400000))
+    assert r["status"] == orc.OPTIMAL
+    yo = yo[:qp.m]
+    for xi in (0.5, 2.0):
+        assert abs(_gap_closed_form(Q, Ap, c, bp, xo, yo, xo, yo, xi)) < 1e-9
+        assert _gap_by_maximisation(Q, Ap, c, bp, xo, yo, xo, yo, xi) < 1e-9
+    # ... and a shifted dual (not a saddle point) does not
+    assert _gap_closed_form(Q, Ap, c, bp, xo, yo + 0.1, xo, yo + 0.1, 2.0) > 1e-4
