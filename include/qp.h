@@ -146,7 +146,8 @@ typedef struct {
     int32_t log_checks;      /* 1: record one qp_check_info per evaluation (qp_get_check_log) */
     int32_t device;          /* HIP device ordinal; default 0 */
     int32_t panels_dual;     /* column panels of A for the dual phase: 0 = automatic (4 when
-                                the gathered vector exceeds 6 MB, else 1), 1 = unpanelled,
+                                the gathered vector exceeds 6 MB, or 1.75 MB with rows of
+                                256 or more entries on average, else 1), 1 = unpanelled,
                                 2/4/8 = panels pinned to groups of 8/np XCDs */
     int32_t panels_primal;   /* same for P = [Q | -A'] in the primal phase */
     int32_t momentum;        /* 1 (default): accelerated PDHG, Algorithm 1 with beta_k = (k+2)/2,

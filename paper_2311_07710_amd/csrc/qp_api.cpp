@@ -314,12 +314,22 @@ struct DevPanels {
 };
 
 // panel count: explicit setting, else 4 (two XCDs per panel) when the gathered
-// vector exceeds 6 MB. Measured: one panel ties or wins up to 4.8 MB (random and
-// equality QPs with n + m up to 6e5, where the gathers still mostly hit L2 and the
-// combine kernel is pure cost); 4 wins among 1/2/4/8 at 8-12 MB (n = 1e6)
-int choose_panels(int32_t setting, int64_t gathered_len) {
+// vector exceeds 6 MB, or exceeds 1.75 MB with rows of at least 256 entries on average.
+// Measured: one panel ties or wins up to 4.8 MB on random and equality QPs (n + m up
+// to 6e5, rows of 4-20 entries), where the gathers still mostly hit L2 and the
+// combine kernel is pure cost; 4 wins among 1/2/4/8 at 8-12 MB (n = 1e6).  With long
+// rows (factor-model portfolio QPs: a thousand factor rows of thousands of entries
+// and the budget row) the row kernel loads a chunk's matrix entries and then gathers,
+// one chunk per workgroup, while the persistent panel kernels overlap the two, and a
+// thousand rows make the combine free: 4 panels take the dual phase of a 1000-factor
+// portfolio from 40.6 to 36.1 us per iteration at 2.5e5 assets (1.9 MB gathered) and
+// from 68.6 to 59.4 us at 5e5 (3.8 MB), but not at 2e5 (1.5 MB: 31.1 vs 32.1 us).
+int choose_panels(int32_t setting, int64_t gathered_len, int64_t nnz, int64_t rows) {
     if (setting == 1 || setting == 2 || setting == 4 || setting == 8) return setting;
-    return gathered_len * 8 > (6 << 20) ? 4 : 1;
+    const int64_t bytes = gathered_len * 8;
+    if (bytes > ((int64_t)6 << 20)) return 4;
+    if (rows > 0 && nnz >= 256 * rows && bytes > ((int64_t)7 << 18)) return 4;
+    return 1;
 }
 
 // copies `count` elements of an input array (host or device) to a host vector
@@ -804,8 +814,8 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
                           (h->uniform_bounds ? 56.0 : 72.0) * (double)n;
     }
     if ((rc = h->partA.upload(hpA)) || (rc = h->partP.upload(hpP))) return rc;
-    h->npA = m > 0 ? choose_panels(h->set.panels_dual, n) : 1;
-    h->npP = choose_panels(h->set.panels_primal, n + m);
+    h->npA = m > 0 ? choose_panels(h->set.panels_dual, n, d->A.nnz, m) : 1;
+    h->npP = choose_panels(h->set.panels_primal, n + m, pnnz, n);
     {
         // the two panel layouts are independent: A's is built on a second thread
         HostPanels pa, pp;
