@@ -319,11 +319,12 @@ struct DevPanels {
 // to 6e5, rows of 4-20 entries), where the gathers still mostly hit L2 and the
 // combine kernel is pure cost; 4 wins among 1/2/4/8 at 8-12 MB (n = 1e6).  With long
 // rows (factor-model portfolio QPs: a thousand factor rows of thousands of entries
-// and the budget row) the row kernel loads a chunk's matrix entries and then gathers,
-// one chunk per workgroup, while the persistent panel kernels overlap the two, and a
-// thousand rows make the combine free: 4 panels take the dual phase of a 1000-factor
-// portfolio from 40.6 to 36.1 us per iteration at 2.5e5 assets (1.9 MB gathered) and
-// from 68.6 to 59.4 us at 5e5 (3.8 MB), but not at 2e5 (1.5 MB: 31.1 vs 32.1 us).
+// and the budget row) the partial sums are a few thousand values, so the XCD-local
+// gather slices pay off from a smaller vector: 4 panels take the dual phase of a
+// 1000-factor portfolio from 40.6 to 36.1 us per iteration at 2.5e5 assets (1.9 MB
+// gathered) and from 68.6 to 59.4 us at 5e5 (3.8 MB), but not at 2e5 (1.5 MB: 31.1 vs
+// 32.1 us).  (The row kernel made persistent and pipelined like the panel kernels,
+// without panels, stays at 69.8 us there: the gain is the slices' L2 hits.)
 int choose_panels(int32_t setting, int64_t gathered_len, int64_t nnz, int64_t rows) {
     if (setting == 1 || setting == 2 || setting == 4 || setting == 8) return setting;
     const int64_t bytes = gathered_len * 8;
