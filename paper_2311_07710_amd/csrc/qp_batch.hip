@@ -496,6 +496,43 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
         const int nlra = a.lrA_off[id + 1] - a.lrA_off[id];
         const int32_t *lrp = a.lrP + a.lrP_off[id];
         const int nlrp = a.lrP_off[id + 1] - a.lrP_off[id];
+        // Matrix cache: with every vector in LDS (LDS_ALL), the rest of the team's LDS
+        // holds the instance's leading slices of sliced A, then of sliced P (whole slices,
+        // so the rows of a wavefront are all cached or all not), and those rows read their
+        // entries from LDS.  A team streams its matrix through one CU's L1 every iteration;
+        // the cached share leaves that path.  Values and order are the global arrays':
+        // results are unchanged.
+        int ca_sl = 0, cp_sl = 0;  // cached slices of A and of P
+        int ca_n = 0, cp_n = 0;    // cached entries
+        const int a_base = m > 0 ? sa_start[0] : 0, p_base = sp_start[0];
+        double *cva = smem, *cvp = smem;
+        int32_t *cca = reinterpret_cast<int32_t *>(smem), *ccp = cca;
+        if (ALL) {
+            int64_t room = ((int64_t)a.lds_doubles - 5 * (int64_t)n - 2 * (int64_t)m) * 8;
+            const int nsa = (m + SLICE - 1) / SLICE, nsp = (n + SLICE - 1) / SLICE;
+            while (ca_sl < nsa && 12 * (int64_t)SLICE * sa_width[ca_sl] <= room) {
+                room -= 12 * (int64_t)SLICE * sa_width[ca_sl];
+                ca_n += SLICE * sa_width[ca_sl];
+                ++ca_sl;
+            }
+            while (cp_sl < nsp && 12 * (int64_t)SLICE * sp_width[cp_sl] <= room) {
+                room -= 12 * (int64_t)SLICE * sp_width[cp_sl];
+                cp_n += SLICE * sp_width[cp_sl];
+                ++cp_sl;
+            }
+            cva = smem + 5 * n + 2 * m;
+            cvp = cva + ca_n;
+            cca = reinterpret_cast<int32_t *>(cvp + cp_n);
+            ccp = cca + ca_n;
+            for (int q = t; q < ca_n; q += NT) {
+                cva[q] = a.sa_val[a_base + q];
+                cca[q] = a.sa_col[a_base + q];
+            }
+            for (int q = t; q < cp_n; q += NT) {
+                cvp[q] = a.sp_val[p_base + q];
+                ccp[q] = a.sp_col[p_base + q];
+            }
+        }
         DevSettings ds = base;
         ds.norm_A = a.normA[id];
         ds.norm_Q = a.normQ[id];
@@ -620,8 +657,10 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
                         ti = rt[i];
                     }
                     const bool mine = len <= LONG_ROW;
-                    const double s = sliced_dot(a.sa_col, a.sa_val, e, w, len,
-                                                [&](int cc) { return xt[cc]; });
+                    const auto gx = [&](int cc) { return xt[cc]; };
+                    const double s = ALL && i / SLICE < ca_sl
+                                         ? sliced_dot(cca, cva, e - a_base, w, len, gx)
+                                         : sliced_dot(a.sa_col, a.sa_val, e, w, len, gx);
                     double yn = y[i] - st.d * (s - bi);
                     if (ti == 1 && yn < 0.0) yn = 0.0;
                     const double ybn = (1.0 - st.w) * ybar[i] + st.w * yn;
@@ -661,9 +700,10 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
                         uj = u[jj];
                     }
                     const bool mine = len <= LONG_ROW;
-                    const double s = sliced_dot(
-                        a.sp_col, a.sp_val, e, w, len,
-                        [&](int cc) { return *(cc < n ? xin + cc : y + (cc - n)); });
+                    const auto gz = [&](int cc) { return *(cc < n ? xin + cc : y + (cc - n)); };
+                    const double s = ALL && jj / SLICE < cp_sl
+                                         ? sliced_dot(ccp, cvp, e - p_base, w, len, gz)
+                                         : sliced_dot(a.sp_col, a.sp_val, e, w, len, gz);
                     const double xo = x[jj];
                     double xn, xb;
                     primal_update(s, st, cj, lj, uj, xo, xbar[jj], xn, xb);
@@ -930,6 +970,7 @@ struct BatchData {
     int num_cu = 256;
     int use_lds = 1;
     int32_t lds_need[NCLASS] = {0, 0, 0, 0};  // doubles of dynamic LDS per class
+    int32_t lds_cap = 0;  // bytes of dynamic LDS a team may have (the matrix cache's limit)
     // one stream per size class (default priority), forked from and joined to `stream`
     hipStream_t cls_stream[NCLASS] = {};
     hipEvent_t ev_fork = nullptr, ev_join[NCLASS] = {};
@@ -1100,6 +1141,26 @@ static int persistent_grid(K kernel, int nt, int count, int num_cu, size_t lds =
     return g < count ? g : count;
 }
 
+// Dynamic LDS of a class whose vectors fit: the cap when the occupancy query gives as
+// many resident teams per CU with it as with the vectors alone (the rest then caches
+// matrix slices), else the vectors' share.
+template <int NT>
+static size_t cache_lds(size_t need, size_t cap, int32_t *lds_doubles) {
+    int occ_need = 0, occ_cap = 0;
+    if (hipFuncSetAttribute((const void *)k_batch<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)cap) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_need, k_batch<NT>, NT, need) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_cap, k_batch<NT>, NT, cap) !=
+            hipSuccess ||
+        occ_cap < 1 || occ_cap < occ_need) {
+        (void)hipGetLastError();
+        return need;
+    }
+    *lds_doubles = (int32_t)(cap / 8);
+    return cap;
+}
+
 // launches one persistent kernel over the instances order[lo, hi) of size class k on
 // stream s, with queue head k (reset beforehand by run_classes)
 static void launch_class(BatchData *bd, BatchDev a, const DevSettings &ds, int nt, int lo, int hi,
@@ -1115,7 +1176,9 @@ static void launch_class(BatchData *bd, BatchDev a, const DevSettings &ds, int n
             hipLaunchKernelGGL(k_batch_norms<NT>, dim3(g), dim3(NT), 0, s, a, maxit, rtol,       \
                                bd->normA_d.as<double>(), bd->normQ_d.as<double>());              \
         } else {                                                                                 \
-            const size_t lds = (size_t)a.lds_doubles * 8;                                        \
+            size_t lds = (size_t)a.lds_doubles * 8;                                              \
+            if (lds > 0 && (size_t)bd->lds_cap > lds)                                            \
+                lds = cache_lds<NT>(lds, (size_t)bd->lds_cap, &a.lds_doubles);                   \
             if (lds > 64 * 1024 &&                                                               \
                 hipFuncSetAttribute((const void *)k_batch<NT>,                                   \
                                     hipFuncAttributeMaxDynamicSharedMemorySize,                  \
@@ -1555,6 +1618,7 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
         int max_lds = 65536;
         (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         const int cap = std::min(max_lds, 160 * 1024) - 8192;  // room for the static LDS
+        bd->lds_cap = cap;
         for (int k = 0; k < NCLASS; ++k) {
             int64_t need = 0;
             for (int32_t id : bd->order[k]) {
