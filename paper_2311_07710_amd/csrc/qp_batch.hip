@@ -212,8 +212,8 @@ __device__ __forceinline__ double row_dot(const int32_t *__restrict__ col,
 // The slice width w (a multiple of 4) is common to the wavefront, so the 64 lanes of
 // each load read consecutive addresses; entries k >= len are padding and are skipped,
 // so the row is added in CSR order exactly as row_dot does.
-template <class F>
-__device__ __forceinline__ double sliced_dot(const int32_t *__restrict__ col,
+template <class C, class F>
+__device__ __forceinline__ double sliced_dot(const C *__restrict__ col,
                                              const double *__restrict__ val, int e, int w,
                                              int len, F src) {
     double s = 0.0;
@@ -500,37 +500,38 @@ __device__ __forceinline__ void solve_instance(const BatchDev &a, const DevSetti
         // holds the instance's leading slices of sliced A, then of sliced P (whole slices,
         // so the rows of a wavefront are all cached or all not), and those rows read their
         // entries from LDS.  A team streams its matrix through one CU's L1 every iteration;
-        // the cached share leaves that path.  Values and order are the global arrays':
-        // results are unchanged.
+        // the cached share leaves that path.  Columns are kept in 16 bits (with its vectors
+        // in LDS an instance has n + m < 65536), 10 bytes an entry.  Values and order are
+        // the global arrays': results are unchanged.
         int ca_sl = 0, cp_sl = 0;  // cached slices of A and of P
         int ca_n = 0, cp_n = 0;    // cached entries
         const int a_base = m > 0 ? sa_start[0] : 0, p_base = sp_start[0];
         double *cva = smem, *cvp = smem;
-        int32_t *cca = reinterpret_cast<int32_t *>(smem), *ccp = cca;
-        if (ALL) {
+        uint16_t *cca = reinterpret_cast<uint16_t *>(smem), *ccp = cca;
+        if (ALL && n + m <= 65535) {
             int64_t room = ((int64_t)a.lds_doubles - 5 * (int64_t)n - 2 * (int64_t)m) * 8;
             const int nsa = (m + SLICE - 1) / SLICE, nsp = (n + SLICE - 1) / SLICE;
-            while (ca_sl < nsa && 12 * (int64_t)SLICE * sa_width[ca_sl] <= room) {
-                room -= 12 * (int64_t)SLICE * sa_width[ca_sl];
+            while (ca_sl < nsa && 10 * (int64_t)SLICE * sa_width[ca_sl] <= room) {
+                room -= 10 * (int64_t)SLICE * sa_width[ca_sl];
                 ca_n += SLICE * sa_width[ca_sl];
                 ++ca_sl;
             }
-            while (cp_sl < nsp && 12 * (int64_t)SLICE * sp_width[cp_sl] <= room) {
-                room -= 12 * (int64_t)SLICE * sp_width[cp_sl];
+            while (cp_sl < nsp && 10 * (int64_t)SLICE * sp_width[cp_sl] <= room) {
+                room -= 10 * (int64_t)SLICE * sp_width[cp_sl];
                 cp_n += SLICE * sp_width[cp_sl];
                 ++cp_sl;
             }
             cva = smem + 5 * n + 2 * m;
             cvp = cva + ca_n;
-            cca = reinterpret_cast<int32_t *>(cvp + cp_n);
+            cca = reinterpret_cast<uint16_t *>(cvp + cp_n);
             ccp = cca + ca_n;
             for (int q = t; q < ca_n; q += NT) {
                 cva[q] = a.sa_val[a_base + q];
-                cca[q] = a.sa_col[a_base + q];
+                cca[q] = (uint16_t)a.sa_col[a_base + q];
             }
             for (int q = t; q < cp_n; q += NT) {
                 cvp[q] = a.sp_val[p_base + q];
-                ccp[q] = a.sp_col[p_base + q];
+                ccp[q] = (uint16_t)a.sp_col[p_base + q];
             }
         }
         DevSettings ds = base;
