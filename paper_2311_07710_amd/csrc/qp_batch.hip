@@ -209,15 +209,18 @@ __device__ __forceinline__ double row_dot(const int32_t *__restrict__ col,
 }
 
 // The same sum over the sliced layout: entry k of this lane's row sits at e + 64 k.
-// The slice width w (a multiple of 4) is common to the wavefront, so the 64 lanes of
+// The slice width w (its longest row) is common to the wavefront, so the 64 lanes of
 // each load read consecutive addresses; entries k >= len are padding and are skipped,
-// so the row is added in CSR order exactly as row_dot does.
+// so the row is added in CSR order exactly as row_dot does.  Entries go four at a time
+// with their loads issued together; the last one to three as one more such group, whose
+// missing entries repeat the first one (a valid column) and are never added.
 template <class C, class F>
 __device__ __forceinline__ double sliced_dot(const C *__restrict__ col,
                                              const double *__restrict__ val, int e, int w,
                                              int len, F src) {
     double s = 0.0;
-    for (int k = 0; k < w; k += 4, e += 4 * SLICE) {
+    int k = 0;
+    for (; k + 4 <= w; k += 4, e += 4 * SLICE) {
         const int c0 = col[e], c1 = col[e + SLICE], c2 = col[e + 2 * SLICE],
                   c3 = col[e + 3 * SLICE];
         const double a0 = val[e], a1 = val[e + SLICE], a2 = val[e + 2 * SLICE],
@@ -227,6 +230,16 @@ __device__ __forceinline__ double sliced_dot(const C *__restrict__ col,
         if (k + 1 < len) s = s + a1 * g1;
         if (k + 2 < len) s = s + a2 * g2;
         if (k + 3 < len) s = s + a3 * g3;
+    }
+    if (k < w) {
+        const int r = w - k;
+        const int e1 = r > 1 ? e + SLICE : e, e2 = r > 2 ? e + 2 * SLICE : e;
+        const int c0 = col[e], c1 = col[e1], c2 = col[e2];
+        const double a0 = val[e], a1 = val[e1], a2 = val[e2];
+        const double g0 = src(c0), g1 = src(c1), g2 = src(c2);
+        if (k < len) s = s + a0 * g0;
+        if (k + 1 < len) s = s + a1 * g1;
+        if (k + 2 < len) s = s + a2 * g2;
     }
     return s;
 }
@@ -965,6 +978,7 @@ struct BatchData {
     DevMem sa_inst, sa_start, sa_width, sa_col, sa_val;  // sliced A (build_sliced)
     DevMem sp_inst, sp_start, sp_width, sp_col, sp_val;  // sliced P
     std::vector<int32_t> order_off;  // offsets of each class in order_d
+    int32_t launch_order[NCLASS] = {NCLASS - 1, NCLASS - 2, NCLASS - 3, NCLASS - 4};
     std::vector<double> h_omega;     // staging of per-solve scalars (outlive async copies)
     std::vector<uint8_t> h_hx, h_hy;
     int wall_khz = 100000;
@@ -1054,8 +1068,8 @@ static BatchDev make_dev(BatchData *bd) {
 // slices of SLICE rows, one row per lane of a wavefront; entry k of the row in lane l
 // of a slice sits at start[slice] + SLICE * k + l, so the lanes of a load read
 // consecutive addresses.  A slice's width is its longest row, rows longer than
-// LONG_ROW left out (the whole team sums those from the CSR arrays), rounded up to a
-// multiple of 4.  Padding holds column 0 and is never added.  src[e] is the CSR entry
+// LONG_ROW left out (the whole team sums those from the CSR arrays).  Padding holds
+// column 0 and is never added.  src[e] is the CSR entry
 // copied to sliced position e (-1 for padding), so values can be gathered on the
 // device after preprocessing has scaled the CSR values.
 struct HostSliced {
@@ -1076,7 +1090,6 @@ static int build_sliced(const std::vector<int32_t> &rp, const std::vector<int32_
                 const int64_t len = rp[r + 1] - rp[r];
                 if (len <= LONG_ROW) w = std::max(w, len);
             }
-            w = (w + 3) / 4 * 4;
             if (pos + w * SLICE > INT32_MAX)
                 return fail(QP_ERR_INVALID_ARGUMENT, "batch too large for the sliced layout");
             h.start.push_back((int32_t)pos);
@@ -1212,7 +1225,8 @@ static int run_classes(BatchData *bd, F launch) {
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, bd->stream, bd->head.as<int32_t>(),
                        NCLASS, bd->clock0.as<int64_t>());
     HIPCHK(hipEventRecord(bd->ev_fork, bd->stream));
-    for (int k = NCLASS - 1; k >= 0; --k) {
+    for (int q = 0; q < NCLASS; ++q) {
+        const int k = bd->launch_order[q];
         HIPCHK(hipStreamWaitEvent(bd->cls_stream[k], bd->ev_fork, 0));
         launch(k, bd->cls_stream[k]);
         HIPCHK(hipEventRecord(bd->ev_join[k], bd->cls_stream[k]));
@@ -1589,16 +1603,32 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
     }
     bd->normA.assign(B, 0.0);
     bd->normQ.assign(B, 0.0);
-    // size classes and queue order (decreasing nonzeros: long instances start first)
+    // Size classes and queue order: decreasing estimated work, so that likely stragglers
+    // start first.  The estimate is the instance's nonzeros times (1 + m_i / n_i)^8: the
+    // rows per variable rank the iteration counts far better than the size does
+    // (Spearman 0.82 against 0.50 for the nonzeros on the 4096-instance MPC batch, whose
+    // slowest instances are underactuated horizons), and the order alone changes no result.
     bd->cls.resize(B);
     bd->order.assign(NCLASS, {});
-    std::vector<int64_t> work(B);
+    std::vector<double> work(B);
     for (int i = 0; i < B; ++i) {
-        const int64_t rows = (bd->var_off[i + 1] - bd->var_off[i]) + (bd->row_off[i + 1] - bd->row_off[i]);
-        bd->cls[i] = class_of(rows);
-        work[i] = (pr[bd->var_off[i + 1]] - pr[bd->var_off[i]]) +
-                  (ar[bd->row_off[i + 1]] - ar[bd->row_off[i]]) + rows;
+        const int64_t nv = bd->var_off[i + 1] - bd->var_off[i];
+        const int64_t mv = bd->row_off[i + 1] - bd->row_off[i];
+        bd->cls[i] = class_of(nv + mv);
+        const double f = 1.0 + (double)mv / (double)std::max<int64_t>(nv, 1);
+        work[i] = (double)((pr[bd->var_off[i + 1]] - pr[bd->var_off[i]]) +
+                           (ar[bd->row_off[i + 1]] - ar[bd->row_off[i]]) + nv + mv) *
+                  (f * f) * (f * f) * (f * f) * (f * f);
         bd->order[bd->cls[i]].push_back(i);
+    }
+    // classes launch in decreasing order of their summed estimated work: the first
+    // launched kernel takes the free CUs first, and the class with most of the work is
+    // the one whose leading instances must not wait
+    {
+        double cw[NCLASS] = {0, 0, 0, 0};
+        for (int i = 0; i < B; ++i) cw[bd->cls[i]] += work[i];
+        std::stable_sort(bd->launch_order, bd->launch_order + NCLASS,
+                         [&](int32_t p, int32_t q) { return cw[p] > cw[q]; });
     }
     std::vector<int32_t> flat;
     bd->order_off.assign(NCLASS + 1, 0);
