@@ -13,8 +13,8 @@ decision and restart application.  value = iterations per second over the K
 timed steps.  Inputs are resident in HBM (copied at qp_create) before timing.
 
 Also reported: hipEvent durations of the dual and primal phases recorded over
-the timed region (settings.profile = 4: direct launches, events around both
-phases of every 4th iteration on the library's stream), the roofline of the
+the timed region (settings.profile = 16: direct launches, events around both
+phases of every 16th iteration on the library's stream), the roofline of the
 dominant (primal) kernel from its algorithmic bytes, wall time to relKKT 1e-4
 and 1e-6, and the CPU oracle's iteration rate on a bounded sample.
 
@@ -73,7 +73,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--graph", action="store_true",
                     help="time with graph replay instead of per-phase hipEvents")
-    ap.add_argument("--profile-every", type=int, default=4,
+    ap.add_argument("--profile-every", type=int, default=16,
                     help="time the phases of every k-th iteration with hipEvents")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched MPC section")
     ap.add_argument("--no-classes", action="store_true",
