@@ -401,6 +401,7 @@ struct qp_handle {
     DevMem partials_a, partials_p, state, table;
     DevMem ipart_a, ipart_p;    // infeasibility partials (when detection is on)
     DevMem kpart_a, kpart_p;    // KKT panel partial sums (2 np m and 4 np n doubles)
+    DevMem zz;                  // (x, x-bar) and (y, y-bar) pairs gathered by the KKT panels
     Vecs vecs{};
     int32_t nslotA = 0, nslotP = 0;
     State *h_state = nullptr;  // pinned ring of status records
@@ -850,6 +851,7 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
     const int64_t slP = std::max<int64_t>(h->nslotP, (n + BS - 1) / BS);
     if (h->npA > 1 && (rc = h->kpart_a.alloc((size_t)2 * h->npA * m * 8))) return rc;
     if (h->npP > 1 && (rc = h->kpart_p.alloc((size_t)4 * h->npP * n * 8))) return rc;
+    if ((h->npA > 1 || h->npP > 1) && (rc = h->zz.alloc((size_t)(n + m) * 16))) return rc;
     if ((rc = h->partials_a.alloc((size_t)(slA + FOLD_SLOTS) * RA_NV * 8)) ||
         (rc = h->partials_p.alloc((size_t)(slP + FOLD_SLOTS) * RP_NV * 8)) ||
         (rc = h->state.alloc(sizeof(State))) || (rc = h->table.alloc(4096 * sizeof(Step))))
@@ -878,6 +880,7 @@ int create_single(const qp_problem_desc *d, qp_handle *h, HostProblem &hp) {
     v.uniform_bounds = h->uniform_bounds;
     v.lo_all = h->lo_all;
     v.hi_all = h->hi_all;
+    v.zz = (h->npA > 1 || h->npP > 1) ? reinterpret_cast<double2 *>(h->zz.p) : nullptr;
     return QP_OK;
 }
 
@@ -911,6 +914,7 @@ DevSettings dev_settings(const qp_handle *h) {
 // column panels when they exist, so the gathers stay in each XCD's L2); *sa and *sp
 // receive the slot counts for launch_decide.
 void enqueue_kkt(qp_handle *h, hipStream_t s, State *st, int32_t *sa, int32_t *sp) {
+    if (h->npA > 1 || h->npP > 1) launch_interleave(s, h->vecs, st, h->n, h->m);
     if (h->npA > 1) {
         *sa = launch_kkt_rows_panels(s, h->panA.view, h->vecs, h->kpart_a.as<double>(),
                                      h->partials_a.as<double>(), st, h->n, h->m);

@@ -136,6 +136,8 @@ struct Vecs {
     const double *dv, *dr;                // preconditioning D2 [n], D1 [m], or nullptr
     int32_t uniform_bounds;               // 1: l_j = lo_all and u_j = hi_all for every j
     double lo_all, hi_all;
+    double2 *zz;                          // [n + m] pairs (x_j, x-bar_j), then (y_i, y-bar_i):
+                                          // the gathers of the KKT panel kernels, or nullptr
 };
 
 // ---- infeasibility certificates (qp_kernels.hip) ----
@@ -176,6 +178,8 @@ void launch_kkt_cols(hipStream_t s, const Blocks &bk, const Csr &P, const Vecs &
                      double *partials, const State *st, int64_t n);
 // KKT products through the column panels (kpart: 2 np m / 4 np n doubles); return the
 // number of partial slots written for launch_decide
+// fills v.zz from x, x-bar, y, y-bar (before the KKT panel kernels)
+void launch_interleave(hipStream_t s, const Vecs &v, const State *st, int64_t n, int64_t m);
 int32_t launch_kkt_rows_panels(hipStream_t s, const Panels &pn, const Vecs &v, double *kpart,
                                double *partials, const State *st, int64_t n, int64_t m);
 int32_t launch_kkt_cols_panels(hipStream_t s, const Panels &pn, const Vecs &v, double *kpart,
