@@ -55,10 +55,7 @@ __device__ __forceinline__ void step_at(const DevSettings &s, double omega, int6
 // kj+1.  Algorithm 1: w = 1/beta_k, theta_{k+1} = (k+1)/(k+2), w_next = 1/beta_{k+1}.
 // Plain PDHG: beta = theta = 1 (x_md = x, x~ = 2x - x_prev) and z-bar is the uniform
 // average of the cycle, w = 1/(k+1).
-__device__ __forceinline__ Step make_step(const DevSettings &s, double omega, int64_t kj,
-                                          double *s_last) {
-    double p, d;
-    step_at(s, omega, kj, s_last, &p, &d);
+__device__ __forceinline__ Step step_record(const DevSettings &s, int64_t kj, double p, double d) {
     Step e;
     e.p = p;
     e.d = d;
@@ -73,6 +70,13 @@ __device__ __forceinline__ Step make_step(const DevSettings &s, double omega, in
     }
     e.pad[0] = e.pad[1] = e.pad[2] = 0.0;
     return e;
+}
+
+__device__ __forceinline__ Step make_step(const DevSettings &s, double omega, int64_t kj,
+                                          double *s_last) {
+    double p, d;
+    step_at(s, omega, kj, s_last, &p, &d);
+    return step_record(s, kj, p, d);
 }
 
 // relKKT of point p (0 = z, 1 = z-bar) from the reduced quantities

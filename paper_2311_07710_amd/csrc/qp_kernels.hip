@@ -631,18 +631,61 @@ __global__ __launch_bounds__(BS) void k_decide(int mode, const double *__restric
         }
         __syncthreads();
     }
-    if (t != 0) return;
-    double ra[RA_NV], rp[RP_NV];
-    for (int v = 0; v < RA_NV; ++v) ra[v] = red[v][0];
-    for (int v = 0; v < RP_NV; ++v) rp[v] = red[RA_NV + v][0];
-    State S = *st;
-    decide_update(mode, ra, rp, S, s, len);
-    if (mode != DECIDE_FALLBACK && !S.done) {
-        double sl = S.s_last;
-        for (int j = 0; j < s.interval; ++j) table[j] = make_step(s, S.omega, S.k + j, &sl);
-        S.s_last = sl;
+    __shared__ State S;
+    if (t == 0) {
+        double ra[RA_NV], rp[RP_NV];
+        for (int v = 0; v < RA_NV; ++v) ra[v] = red[v][0];
+        for (int v = 0; v < RP_NV; ++v) rp[v] = red[RA_NV + v][0];
+        S = *st;
+        decide_update(mode, ra, rp, S, s, len);
     }
-    *st = S;
+    __syncthreads();
+    if (mode != DECIDE_FALLBACK && !S.done) {
+        // The next interval's step table, the same values as make_step called in order:
+        // with the Sec. 6 rule only the scale's min-recurrence is sequential (thread 0,
+        // a multiply and a compare per entry); the caps, the growth factors and each
+        // entry's divisions are computed by the whole workgroup.
+        const double om = S.omega;
+        const int64_t k0 = S.k;
+        if (s.momentum && s.restart_mode != MODE_FIXED_K) {
+            __shared__ double cap[BS], grow[BS];
+            double sl = S.s_last;  // thread 0's carry
+            for (int c0 = 0; c0 < s.interval; c0 += BS) {
+                const int j = c0 + t;
+                const int64_t kj = k0 + j;
+                if (j < s.interval) {
+                    cap[t] = pdqp_cap(s, om, kj);
+                    grow[t] = kj > 0 ? 1.0 + 1.0 / (double)kj : 0.0;
+                }
+                __syncthreads();
+                if (t == 0) {
+                    const int cnt = s.interval - c0 < BS ? s.interval - c0 : BS;
+                    for (int i = 0; i < cnt; ++i) {
+                        double sk = cap[i];
+                        if (k0 + c0 + i > 0) {
+                            const double grown = grow[i] * sl;
+                            sk = grown < sk ? grown : sk;
+                        }
+                        sl = sk;
+                        cap[i] = sk;
+                    }
+                }
+                __syncthreads();
+                if (j < s.interval) table[j] = step_record(s, kj, cap[t] / om, cap[t] * om);
+                __syncthreads();
+            }
+            if (t == 0) S.s_last = sl;
+        } else {
+            // no recurrence: every entry is independent
+            for (int j = t; j < s.interval; j += BS) {
+                double sl = S.s_last;
+                table[j] = make_step(s, om, k0 + j, &sl);
+                if (j == s.interval - 1) S.s_last = sl;
+            }
+            __syncthreads();
+        }
+    }
+    if (t == 0) *st = S;
 }
 
 // ---------------------------------------------------------------------------
