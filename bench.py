@@ -101,7 +101,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calibrate_copy:
-        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        src = torch.empty(32 << 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
@@ -109,7 +109,7 @@ def main():
         log("[bench] calibration copy: 256 MiB read + 256 MiB written")
         del src, dst
     # measured streaming bandwidth: a plain 1 GiB device-to-device copy (read + write)
-    src = torch.ones(128 << 20, dtype=torch.float64, device="cuda")
+    src = torch.empty(128 << 20, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     copy_gbs = 0.0
@@ -331,13 +331,15 @@ def bench_batch(log):
     m_i = np.diff(batch.row_off)
     a_nnz = np.diff(batch.a_rowptr[batch.row_off].astype(np.int64))
     q_nnz = np.diff(batch.q_rowptr[batch.var_off].astype(np.int64))
-    # bytes one iteration of instance i reads from memory beyond its team's LDS: the rows
+    # bytes one iteration of instance i reads besides its LDS-resident iterates: the rows
     # of A and of P = [Q | -A'] (8 B value + 4 B column per nonzero, 4 B row pointers), and
-    # c, l, u (24 B per variable), b and the row type (9 B per row); the iterates live in LDS
+    # c, l, u (24 B per variable), b and the row type (9 B per row).  The leading slices of
+    # the rows come from the team's LDS cache where it has room, so as memory traffic this
+    # is an upper bound.
     it_bytes = 12.0 * (2 * a_nnz + q_nnz) + 4.0 * (n_i + m_i + 2) + 24.0 * n_i + 9.0 * m_i
     # memory-side ceiling for this access pattern: a device copy of a buffer that the L2s
     # and the 256 MB MALL hold (64 MiB read + 64 MiB written, repeated)
-    src = torch.ones(8 << 20, dtype=torch.float64, device="cuda")
+    src = torch.empty(8 << 20, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
@@ -404,7 +406,9 @@ def bench_batch(log):
                              "note": "each instance's iteration is a chain of dependent loads "
                                      "and barriers on one workgroup; the makespan is the "
                                      "slowest instance's iterations times its per-iteration "
-                                     "latency",
+                                     "latency; achieved counts every matrix and data byte an "
+                                     "iteration reads, also those served by the LDS matrix "
+                                     "cache, so as memory traffic it is an upper bound",
                              "achieved": pre["GBps"], "peak": mall_gbs, "unit": "GB/s",
                              "peak_kind": "measured device copy of a 64 MiB buffer (L2/MALL "
                                           "resident), read + write",
