@@ -16,8 +16,16 @@
 // host into blocks of <= NNZ_BLK nonzeros and <= BS rows; a workgroup streams
 // its nonzeros with coalesced loads, gathers the vector entries
 // and stages the products in LDS, then each row is summed in CSR order
-// (several lanes per row only when a block holds few rows).  HBM-bound: no
-// MFMA anywhere on this path.
+// (several lanes per row only when a block holds few rows).
+//
+// Large instances run both phases on column panels (the second half of this file):
+// the columns are split into ranges pinned to groups of XCDs so each XCD gathers from
+// a slice that stays in its L2; persistent, software-pipelined k_panel_spmv<0/1> write
+// per-panel row sums that k_dual_combine / k_primal_combine add in panel order before
+// the same epilogues.  The KKT evaluation then gathers (x, x-bar) and (y, y-bar) as
+// 16-byte pairs (k_interleave, k_panel_kkt<0/1>).  The path is bound by HBM streams
+// and, on the large instances, by the L2 request rate of the random gathers: no MFMA
+// anywhere on it.
 #include <math.h>
 
 #include "qp_decide.h"
