@@ -157,9 +157,36 @@ static int check_validation() {
     return bad ? 1 : 0;
 }
 
+// The automatic panel count: explicit settings kept; 4 panels above 6 MB of gathered
+// vector; between 1.75 and 6 MB only for rows of at least 256 entries on average.
+static int check_choose_panels() {
+    struct Case { int32_t setting; int64_t len, nnz, rows; int want; };
+    const int64_t MB = 1 << 20;
+    const Case cases[] = {
+        {1, 10 * MB, 1000, 10, 1}, {2, 100, 100, 10, 2}, {4, 100, 100, 10, 4},
+        {8, 100, 100, 10, 8},                                  // explicit
+        {0, 6 * MB / 8 + 1, 10, 10, 4}, {0, 6 * MB / 8, 10, 10, 1},   // size rule at 6 MB
+        {0, 4 * MB / 8, 256 * 1001, 1001, 4},                 // long rows, 4 MB
+        {0, 4 * MB / 8, 255 * 1001, 1001, 1},                 // rows just too short
+        {0, 7 * MB / 32 + 1, 5000 * 1001, 1001, 4},           // long rows above 1.75 MB
+        {0, 7 * MB / 32, 5000 * 1001, 1001, 1},               // long rows at 1.75 MB
+        {0, 4 * MB / 8, 1000, 0, 1},                          // no rows
+    };
+    for (const Case &c : cases) {
+        const int got = choose_panels(c.setting, c.len, c.nnz, c.rows);
+        if (got != c.want) {
+            fprintf(stderr, "choose_panels(%d, %lld, %lld, %lld) = %d, want %d\n", c.setting,
+                    (long long)c.len, (long long)c.nnz, (long long)c.rows, got, c.want);
+            return 1;
+        }
+    }
+    return 0;
+}
+
 int main() {
     std::mt19937_64 g(11);
     if (check_validation()) return 1;
+    if (check_choose_panels()) return 1;
     if (check_build_p(g) || check_panels(g)) return 1;
     printf("all ok\n");
     return 0;
