@@ -509,16 +509,25 @@ int estimate_norms(qp_handle *h) {
     const int np_n = dot_nparts(n), np_m = dot_nparts(std::max<int64_t>(m, 1));
     int rc;
     if ((rc = v.alloc(n * 8)) || (rc = z.alloc(n * 8)) || (rc = w.alloc(std::max<int64_t>(m, 1) * 8)) ||
-        (rc = parts.alloc(1024 * 8)))
+        (rc = parts.alloc(2048 * 8)))
         return rc;
-    std::vector<double> hp(1024);
-    auto dot = [&](const double *a, const double *b, int64_t len, int np, double *out) -> int {
-        launch_dot_partials(s, a, b, len, parts.as<double>(), np);
-        HIPCHK(hipMemcpyAsync(hp.data(), parts.p, np * 8, hipMemcpyDeviceToHost, s));
+    std::vector<double> hp(2048);
+    // the two dot products of a step: partials of a1.b1 in parts[0, np1) and of a2.b2 in
+    // parts[1024, 1024 + np2) (at most 1024 partials each), one copy and one host wait per
+    // step; each is then summed on the host in partial order
+    auto dots = [&](const double *a1, const double *b1, int64_t len1, int np1, double *out1,
+                    const double *a2, const double *b2, int64_t len2, int np2,
+                    double *out2) -> int {
+        launch_dot_partials(s, a1, b1, len1, parts.as<double>(), np1);
+        launch_dot_partials(s, a2, b2, len2, parts.as<double>() + 1024, np2);
+        HIPCHK(hipMemcpyAsync(hp.data(), parts.p, (size_t)(1024 + np2) * 8,
+                              hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        double acc = 0.0;
-        for (int i = 0; i < np; ++i) acc = acc + hp[i];
-        *out = acc;
+        double acc1 = 0.0, acc2 = 0.0;
+        for (int i = 0; i < np1; ++i) acc1 = acc1 + hp[i];
+        for (int i = 0; i < np2; ++i) acc2 = acc2 + hp[1024 + i];
+        *out1 = acc1;
+        *out2 = acc2;
         return QP_OK;
     };
     const int maxit = h->set.power_iter_max;
@@ -532,11 +541,12 @@ int estimate_norms(qp_handle *h) {
             for (int it = 1; it <= maxit; ++it) {
                 launch_spmv_plain(s, h->partA.view, h->A, v.as<double>(), nullptr, n,
                                   w.as<double>(), 1.0);
-                if ((rc = dot(w.as<double>(), w.as<double>(), m, np_m, &lam))) return rc;
                 launch_spmv_plain(s, h->partP.view, h->P, nullptr, w.as<double>(), n,
                                   z.as<double>(), -1.0);
                 double nz2;
-                if ((rc = dot(z.as<double>(), z.as<double>(), n, np_n, &nz2))) return rc;
+                if ((rc = dots(w.as<double>(), w.as<double>(), m, np_m, &lam, z.as<double>(),
+                               z.as<double>(), n, np_n, &nz2)))
+                    return rc;
                 const double nz = std::sqrt(nz2);
                 if (nz == 0.0) break;
                 launch_div(s, v.as<double>(), z.as<double>(), n, nz);
@@ -555,9 +565,10 @@ int estimate_norms(qp_handle *h) {
         for (int it = 1; it <= maxit; ++it) {
             launch_spmv_plain(s, h->partP.view, h->P, v.as<double>(), nullptr, n, z.as<double>(),
                               1.0);
-            if ((rc = dot(v.as<double>(), z.as<double>(), n, np_n, &lam))) return rc;
             double nw2;
-            if ((rc = dot(z.as<double>(), z.as<double>(), n, np_n, &nw2))) return rc;
+            if ((rc = dots(v.as<double>(), z.as<double>(), n, np_n, &lam, z.as<double>(),
+                           z.as<double>(), n, np_n, &nw2)))
+                return rc;
             const double nw = std::sqrt(nw2);
             if (nw == 0.0) break;
             launch_div(s, v.as<double>(), z.as<double>(), n, nw);
