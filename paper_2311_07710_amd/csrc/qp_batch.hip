@@ -1217,14 +1217,17 @@ static void launch_class(BatchData *bd, BatchDev a, const DevSettings &ds, int n
 // Runs launch(k, stream) for every size class, each on its own stream so that the
 // classes overlap: when the workgroups of one persistent launch run out of
 // instances they exit and the next class's workgroups take their place, instead of
-// the GPU idling behind one class's slowest instance.  The largest class starts
-// first (its instances are the longest per iteration).  The caller's stream waits
-// for all of them.
+// the GPU idling behind one class's slowest instance.  The class with the most
+// estimated work starts first.  The caller's stream waits for all of them.
 template <class F>
 static int run_classes(BatchData *bd, F launch) {
     hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, bd->stream, bd->head.as<int32_t>(),
                        NCLASS, bd->clock0.as<int64_t>());
     HIPCHK(hipEventRecord(bd->ev_fork, bd->stream));
+    // Wait for the reset (and the uploads before it) here: while it is pending, every class
+    // kernel gets enqueued behind the fork, all become ready at once and their workgroups
+    // interleave, so the first class no longer takes the free CUs first.
+    HIPCHK(hipStreamSynchronize(bd->stream));
     for (int q = 0; q < NCLASS; ++q) {
         const int k = bd->launch_order[q];
         HIPCHK(hipStreamWaitEvent(bd->cls_stream[k], bd->ev_fork, 0));
