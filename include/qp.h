@@ -127,16 +127,17 @@ typedef struct {
     int32_t check_every;     /* KKT evaluation cadence for ADAPTIVE/HALVING/NONE; default 64 */
     int32_t restart_mode;    /* QP_RESTART_*; default ADAPTIVE */
     int32_t fixed_K;         /* restart frequency for FIXED_K; default 100 */
-    double beta_sufficient;  /* Sec. 6 restart (i); default 0.2 */
-    double beta_necessary;   /* Sec. 6 restart (ii); default 0.8 */
-    double beta_artificial;  /* Sec. 6 restart (iii); default 0.36 */
-    double pw_smoothing;     /* Sec. 6 primal-weight smoothing theta; default 0.2 */
-    double eps_zero;         /* Sec. 6 epsilon_zero; default 1e-10 */
+    double beta_sufficient;  /* Sec. 6 restart (i); default 0.2; in (0, 1] */
+    double beta_necessary;   /* Sec. 6 restart (ii); default 0.8; in (0, 1] */
+    double beta_artificial;  /* Sec. 6 restart (iii); default 0.36; in (0, 1] */
+    double pw_smoothing;     /* Sec. 6 primal-weight smoothing theta; default 0.2; in [0, 1] */
+    double eps_zero;         /* Sec. 6 epsilon_zero; default 1e-10; >= 0 */
     double step_safety;      /* Sec. 6 step-size factor 0.99 */
     double norm_A;           /* > 0: use as ||A||_2 instead of power iteration */
     double norm_Q;           /* > 0: use as ||Q||_2 instead of power iteration */
-    int32_t power_iter_max;  /* default 1000 */
-    double power_iter_rtol;  /* default 1e-7 */
+    int32_t power_iter_max;  /* power-iteration steps at most; default 1000; >= 1 */
+    double power_iter_rtol;  /* stop when the estimate moves by at most rtol (relative);
+                                default 1e-7; >= 0 */
     int32_t warm_fallback;   /* 1 (default): a warm start is used only if its relKKT is
                                 below that of the cold start */
     int32_t use_graph;       /* 1 (default): replay one captured hipGraph per check interval */

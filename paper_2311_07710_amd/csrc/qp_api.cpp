@@ -487,6 +487,20 @@ int check_settings(const qp_settings &s) {
     if (s.check_every > 4096 || (s.restart_mode == QP_RESTART_FIXED_K && s.fixed_K > 4096))
         return fail(QP_ERR_INVALID_ARGUMENT, "evaluation interval above 4096 is not supported");
     if (!(s.step_safety > 0.0)) return fail(QP_ERR_INVALID_ARGUMENT, "step_safety must be > 0");
+    // Sec. 6 restart criteria compare relKKT against fractions of earlier values, and
+    // the primal-weight update is a convex combination in log space
+    if (!(s.beta_sufficient > 0.0 && s.beta_sufficient <= 1.0) ||
+        !(s.beta_necessary > 0.0 && s.beta_necessary <= 1.0) ||
+        !(s.beta_artificial > 0.0 && s.beta_artificial <= 1.0))
+        return fail(QP_ERR_INVALID_ARGUMENT, "beta_sufficient, beta_necessary and "
+                                             "beta_artificial must be in (0, 1]");
+    if (!(s.pw_smoothing >= 0.0 && s.pw_smoothing <= 1.0))
+        return fail(QP_ERR_INVALID_ARGUMENT, "pw_smoothing must be in [0, 1]");
+    if (!(s.eps_zero >= 0.0)) return fail(QP_ERR_INVALID_ARGUMENT, "eps_zero must be >= 0");
+    if (s.power_iter_max < 1)
+        return fail(QP_ERR_INVALID_ARGUMENT, "power_iter_max must be >= 1");
+    if (!(s.power_iter_rtol >= 0.0))
+        return fail(QP_ERR_INVALID_ARGUMENT, "power_iter_rtol must be >= 0");
     if (s.momentum != 0 && s.momentum != 1)
         return fail(QP_ERR_INVALID_ARGUMENT, "momentum must be 0 or 1");
     if (s.profile < 0) return fail(QP_ERR_INVALID_ARGUMENT, "profile must be >= 0");

@@ -120,7 +120,18 @@ def test_malformed_input_rejected_on_host(mutate, needle):
                                        ({"restart_mode": 9}, "restart_mode"),
                                        ({"restart_mode": 1, "fixed_K": 0}, "fixed_K"),
                                        ({"eps": -1.0}, "eps"),
-                                       ({"momentum": 2}, "momentum")])
+                                       ({"momentum": 2}, "momentum"),
+                                       ({"beta_sufficient": 0.0}, "beta_sufficient"),
+                                       ({"beta_necessary": 1.5}, "beta_necessary"),
+                                       ({"beta_artificial": float("nan")}, "beta_artificial"),
+                                       ({"pw_smoothing": -0.1}, "pw_smoothing"),
+                                       ({"pw_smoothing": 1.01}, "pw_smoothing"),
+                                       ({"eps_zero": -1.0}, "eps_zero"),
+                                       ({"power_iter_max": 0}, "power_iter_max"),
+                                       ({"power_iter_rtol": -1e-7}, "power_iter_rtol"),
+                                       ({"step_safety": 0.0}, "step_safety"),
+                                       ({"ruiz_iters": 101}, "ruiz_iters"),
+                                       ({"eps_infeasible": 0.0}, "eps_infeasible")])
 def test_bad_settings_rejected(kw, needle):
     rc, msg = _create_rc(_tiny(), **kw)
     assert rc == B.QP_ERR_INVALID_ARGUMENT and needle in msg

@@ -129,6 +129,26 @@ def test_batch_power_iteration_norms(orc, qpa):
         assert gQ[i] == pytest.approx(nQ, rel=1e-5)
 
 
+def test_batch_power_iteration_limits(orc, qpa):
+    """power_iter_max reaches the batched power iteration: after three steps every
+    instance's norms equal the oracle's three-step estimates, which for some instances
+    differ from the converged ones."""
+    insts = _mixed_batch()
+    batch = qpgen.concat_batch(insts)
+    bs = qpa.BatchSolver(batch, qpa.Settings(power_iter_max=3, power_iter_rtol=0.0))
+    gA, gQ = bs.norms()
+    bs.close()
+    moved = 0
+    for i, qp in enumerate(insts):
+        nA, _ = orc.norm_A(qp, 3, 0.0)
+        nQ, _ = orc.norm_Q(qp, 3, 0.0)
+        fA, _ = orc.norm_A(qp, 1000, 1e-7)
+        moved += abs(nA - fA) > 1e-6 * fA
+        assert gA[i] == pytest.approx(nA, rel=1e-9, abs=1e-12)
+        assert gQ[i] == pytest.approx(nQ, rel=1e-9, abs=1e-12)
+    assert moved > 0
+
+
 def test_batch_team_sizes_agree(orc, qpa):
     """Every team size gives the same iterates (row sums are per thread in CSR order);
     the autotuner returns valid team sizes."""

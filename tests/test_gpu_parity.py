@@ -43,19 +43,22 @@ def _norms(orc, qp):
 
 def _pair(orc, qpa, qp, *, eps=1e-6, max_iter=200000, check_every=64, mode=0, fixed_K=100,
           x0=None, y0=None, omega0=0.0, warm_fallback=1, use_graph=1, norms=None, log=True,
-          panels=(0, 0), momentum=1, precondition=False, scaling_out=None, detect=False):
+          panels=(0, 0), momentum=1, precondition=False, scaling_out=None, detect=False,
+          ruiz=10, extra=None):
     """Oracle and GPU runs of the same instance and settings.  With precondition the
-    oracle solves its own Sec. 5 scaling of qp (relKKT on qp) and the GPU scales on the
-    device; norms are then those of the scaled problem."""
+    oracle solves its own Sec. 5 scaling of qp (relKKT on qp, `ruiz` Ruiz passes) and the
+    GPU scales on the device; norms are then those of the scaled problem.  `extra`: more
+    settings, given to both sides under the same names."""
+    extra = extra or {}
     if precondition:
-        sc, dv, dr = orc.precondition(qp)
+        sc, dv, dr = orc.precondition(qp, ruiz_iters=ruiz)
         nA, nQ = norms if norms is not None else _norms(orc, sc)
     else:
         nA, nQ = norms if norms is not None else _norms(orc, qp)
     os_ = orc.OracleSettings(eps=eps, max_iter=max_iter, check_every=check_every,
                              restart_mode=mode, fixed_K=fixed_K, norm_A=nA, norm_Q=nQ,
                              warm_fallback=warm_fallback, momentum=momentum,
-                             detect_infeasibility=1 if detect else 0)
+                             detect_infeasibility=1 if detect else 0, **extra)
     if precondition:
         xo, yo, ro, lo = orc.solve_scaled(sc, qp, dv, dr, os_, x0=x0, y0=y0, omega0=omega0,
                                           log_cap=100000)
@@ -65,8 +68,8 @@ def _pair(orc, qpa, qp, *, eps=1e-6, max_iter=200000, check_every=64, mode=0, fi
                       fixed_K=fixed_K, norm_A=nA, norm_Q=nQ, warm_fallback=warm_fallback,
                       use_graph=use_graph, log_checks=1 if log else 0,
                       panels_dual=panels[0], panels_primal=panels[1], momentum=momentum,
-                      precondition=1 if precondition else 0,
-                      detect_infeasibility=1 if detect else 0)
+                      precondition=1 if precondition else 0, ruiz_iters=ruiz,
+                      detect_infeasibility=1 if detect else 0, **extra)
     with qpa.Solver(qp, gs) as s:
         if scaling_out is not None:
             scaling_out.append((s.scaling(), (dv, dr) if precondition else None))
@@ -144,6 +147,55 @@ def test_power_iteration_norms(orc, qpa, maker):
         gA, gQ = s.norms()
     assert gA == pytest.approx(nA, rel=1e-5)
     assert gQ == pytest.approx(nQ, rel=1e-5)
+
+
+@pytest.mark.parametrize("maxit,rtol", [(3, 0.0), (200, 1e-3)])
+def test_power_iteration_limits(orc, qpa, maxit, rtol):
+    """power_iter_max and power_iter_rtol reach the device: stopped after `maxit` steps,
+    or once the estimate moves by at most rtol, the GPU's norms equal the oracle's under
+    the same limits (the same iteration from the same start), which differ from the
+    converged norms."""
+    qp = qpgen.large_random_qp(seed=2, n=30000, m=15000)
+    nA, itA = orc.norm_A(qp, maxit, rtol)
+    nQ, itQ = orc.norm_Q(qp, maxit, rtol)
+    fA, fQ = _norms(orc, qp)
+    print(f"  oracle: ||A|| {nA:.12g} after {itA} steps, ||Q|| {nQ:.12g} after {itQ}", flush=True)
+    assert abs(nA - fA) > 1e-6 * fA and abs(nQ - fQ) > 1e-6 * fQ
+    with qpa.Solver(qp, qpa.Settings(power_iter_max=maxit, power_iter_rtol=rtol)) as s:
+        gA, gQ = s.norms()
+    assert gA == pytest.approx(nA, rel=1e-9)
+    assert gQ == pytest.approx(nQ, rel=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# the method's constants as settings (Sec. 6 restart criteria, primal-weight
+# smoothing, step-size factor, epsilon_zero).  Each value below changes the oracle's
+# trajectory on these instances, so agreement with the oracle run at that value shows
+# that the GPU applied it.
+# ---------------------------------------------------------------------------
+_CONSTANTS = {
+    "restart_criteria": {"beta_sufficient": 0.1, "beta_necessary": 0.9, "beta_artificial": 1.0},
+    "pw_smoothing": {"pw_smoothing": 0.6},
+    "step_safety": {"step_safety": 0.9},
+    "eps_zero": {"eps_zero": 1e6},
+}
+
+
+@pytest.mark.parametrize("name", sorted(_CONSTANTS))
+@pytest.mark.parametrize("seed", [1, 7])
+def test_method_constants_as_settings(orc, qpa, name, seed):
+    qp = qpgen.tiny_random_qp(seed)
+    norms = _norms(orc, qp)
+    extra = _CONSTANTS[name]
+    base = orc.solve(qp, orc.OracleSettings(eps=1e-6, norm_A=norms[0], norm_Q=norms[1]),
+                     log_cap=100000)
+    o, g = _pair(orc, qpa, qp, eps=1e-6, norms=norms, extra=extra)
+
+    def trace(log):
+        return [(e["total"], e["restarted"], e["r_cur"]) for e in log]
+
+    assert trace(o[3]) != trace(base[3])
+    _assert_parity(orc, qp, o, g)
 
 
 # ---------------------------------------------------------------------------

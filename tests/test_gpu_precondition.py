@@ -50,6 +50,24 @@ def test_device_scaling_matches_oracle(orc, qpa, maker):
     np.testing.assert_allclose(gr, dr, rtol=1e-14)
 
 
+@pytest.mark.parametrize("ruiz", [0, 1, 3])
+def test_ruiz_pass_count_setting(orc, qpa, ruiz):
+    """ruiz_iters (the Ruiz passes before the l2 and Pock-Chambolle steps) reaches the
+    device: the scaling equals the oracle's for the same count, which differs from the
+    default count's, and the preconditioned solve keeps parity."""
+    qp = _badly_scaled()
+    _, dv, dr = orc.precondition(qp, ruiz_iters=ruiz)
+    _, dv10, dr10 = orc.precondition(qp)
+    assert np.max(np.abs(dr - dr10)) > 1e-6 * np.max(np.abs(dr10))
+    with qpa.Solver(qp, qpa.Settings(precondition=1, ruiz_iters=ruiz, norm_A=1.0,
+                                     norm_Q=1.0)) as s:
+        gv, gr = s.scaling()
+    np.testing.assert_allclose(gv, dv, rtol=1e-14)
+    np.testing.assert_allclose(gr, dr, rtol=1e-14)
+    o, g = _pair(orc, qpa, qp, eps=1e-6, precondition=True, ruiz=ruiz)
+    _assert_parity(orc, qp, o, g)
+
+
 @pytest.mark.parametrize("maker,eps", [(lambda: qpgen.tiny_random_qp(1), 1e-6),
                                        (_badly_scaled, 1e-6),
                                        (lambda: qpgen.portfolio_family(seed=5, count=2).instance(0),
