@@ -61,13 +61,13 @@ def _long_row_instance(seed=11, n=300, m=160):
 
 
 def _oracle_all(orc, insts, eps, max_iter=200000, x0s=None, y0s=None, fb=1, momentum=1,
-                restart_mode=0):
+                restart_mode=0, extra=None):
     out = []
     for i, qp in enumerate(insts):
         nA, _ = orc.norm_A(qp, 1000, 1e-7)
         nQ, _ = orc.norm_Q(qp, 1000, 1e-7)
         s = orc.OracleSettings(eps=eps, max_iter=max_iter, norm_A=nA, norm_Q=nQ, warm_fallback=fb,
-                               momentum=momentum, restart_mode=restart_mode)
+                               momentum=momentum, restart_mode=restart_mode, **(extra or {}))
         x, y, r, _ = orc.solve(qp, s, x0=None if x0s is None else x0s[i],
                                y0=None if y0s is None else y0s[i])
         out.append((x, y, r, nA, nQ))
@@ -100,6 +100,27 @@ def test_batch_matches_oracle_per_instance(orc, qpa):
     with_norms.set_norms([r[3] for r in ref], [r[4] for r in ref])
     xg, yg, rg = with_norms.solve()
     with_norms.close()
+    _compare(batch, xg, yg, rg, ref)
+
+
+@pytest.mark.parametrize("extra,max_iter", [
+    ({"beta_sufficient": 0.15, "beta_necessary": 0.85, "beta_artificial": 0.5,
+      "pw_smoothing": 0.3, "step_safety": 0.95}, 200000),
+    ({"eps_zero": 1e6}, 8192)], ids=["sec6_constants", "eps_zero"])
+def test_batch_method_constants_as_settings(orc, qpa, extra, max_iter):
+    """The Sec. 6 constants given as settings reach the persistent kernel (and the
+    host's initial primal weight): at values that change the oracle's iteration counts,
+    every instance matches the oracle run with the same values (with epsilon_zero above
+    the norms the primal weight stays 1 and slow instances stop at the limit)."""
+    insts = _mixed_batch()[:8] + [_long_row_instance()]
+    batch = qpgen.concat_batch(insts)
+    ref = _oracle_all(orc, insts, eps=1e-6, max_iter=max_iter, extra=extra)
+    base = _oracle_all(orc, insts, eps=1e-6, max_iter=max_iter)
+    assert any(r[2]["iterations"] != b[2]["iterations"] for r, b in zip(ref, base))
+    bs = qpa.BatchSolver(batch, qpa.Settings(eps=1e-6, max_iter=max_iter, **extra))
+    bs.set_norms([r[3] for r in ref], [r[4] for r in ref])
+    xg, yg, rg = bs.solve()
+    bs.close()
     _compare(batch, xg, yg, rg, ref)
 
 
