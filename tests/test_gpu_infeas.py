@@ -35,6 +35,26 @@ def test_infeasible_status_matches_oracle(orc, qpa, kind, seed, pre):
     assert g[2]["iterations"] == o[2]["iterations"]
 
 
+@pytest.mark.parametrize("eps_inf", [1e-4, 1e-12])
+@pytest.mark.parametrize("kind", ["primal", "dual"])
+def test_certificate_tolerance_setting(orc, qpa, kind, eps_inf):
+    """eps_infeasible reaches the device: at a tolerance that moves the oracle's
+    detection to another evaluation than the default's, the GPU detects at that one."""
+    qp = (qpgen.primal_infeasible_qp if kind == "primal" else qpgen.dual_infeasible_qp)(1)
+    nA, _ = orc.norm_A(qp, 1000, 1e-7)
+    nQ, _ = orc.norm_Q(qp, 1000, 1e-7)
+    base = orc.solve(qp, orc.OracleSettings(eps=1e-6, max_iter=100000, norm_A=nA, norm_Q=nQ,
+                                            detect_infeasibility=1))[2]
+    o, g = _pair(orc, qpa, qp, eps=1e-6, max_iter=100000, detect=True, norms=(nA, nQ),
+                 extra={"eps_infeasible": eps_inf})
+    want = orc.PRIMAL_INFEASIBLE if kind == "primal" else orc.DUAL_INFEASIBLE
+    print(f"  {qp.name}: default detects at {base['iterations']}, oracle at "
+          f"{o[2]['iterations']}, gpu at {g[2]['iterations']}", flush=True)
+    assert o[2]["status"] == want and o[2]["iterations"] != base["iterations"]
+    assert g[2]["status"] == want
+    assert g[2]["iterations"] == o[2]["iterations"]
+
+
 @pytest.mark.parametrize("panels", [(1, 1), (4, 4)])
 @pytest.mark.parametrize("kind", ["primal", "dual"])
 def test_larger_instances_with_panels(orc, qpa, kind, panels):
