@@ -1214,6 +1214,31 @@ static void launch_class(BatchData *bd, BatchDev a, const DevSettings &ds, int n
 #undef QPB_LAUNCH
 }
 
+// Gives each size class's hardware queue its private-memory (scratch) backing at create.
+// The solve kernel's out-of-line calls and spilled registers use private memory, and the
+// first dispatch of such a kernel on a queue has the runtime allocate it, which otherwise
+// falls into the first solve and delays the start of that class.  Every class stream runs
+// k_batch<1024> (the largest private segment per lane) at its full persistent grid over
+// an empty queue: each workgroup takes no instance and exits.  The queue heads it counts
+// up are reset before every solve.
+static int warm_class_queues(BatchData *bd) {
+    BatchDev a = make_dev(bd);
+    a.order = bd->order_d.as<int32_t>();
+    a.order_count = 0;
+    a.lds_doubles = 0;
+    DevSettings ds;
+    std::memset(&ds, 0, sizeof(ds));
+    const int g = persistent_grid(k_batch<1024>, 1024, 1 << 30, bd->num_cu);
+    for (int k = 0; k < NCLASS; ++k) {
+        if (bd->order_off[k + 1] == bd->order_off[k]) continue;
+        a.head = bd->head.as<int32_t>() + k;
+        hipLaunchKernelGGL(k_batch<1024>, dim3(g), dim3(1024), 0, bd->cls_stream[k], a, ds);
+    }
+    HIPCHK(hipGetLastError());
+    for (int k = 0; k < NCLASS; ++k) HIPCHK(hipStreamSynchronize(bd->cls_stream[k]));
+    return QP_OK;
+}
+
 // Runs launch(k, stream) for every size class, each on its own stream so that the
 // classes overlap: when the workgroups of one persistent launch run out of
 // instances they exit and the next class's workgroups take their place, instead of
@@ -1705,6 +1730,10 @@ int create_batch(const qp_problem_desc *d, const qp_settings *s, hipStream_t str
             delete bd;
             return fail(QP_ERR_INVALID_ARGUMENT, "instance %d has ||A|| = ||Q|| = 0", i);
         }
+    if ((rc = warm_class_queues(bd))) {
+        delete bd;
+        return rc;
+    }
     *out = bd;
     return QP_OK;
 }
