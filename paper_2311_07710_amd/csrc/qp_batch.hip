@@ -83,10 +83,16 @@ constexpr int SLICE = 64;  // rows per slice of the sliced layout: one per lane 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double bmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
-template <int NT>
-__device__ void team_reduce(double *cv, int nv, int nmax_first, double *red /*[32][NT/64]*/) {
+// Team-wide reduction of NV values, the first nmax_first by maximum and the rest by sum;
+// result in thread 0's cv.  NV is a compile-time count so that cv, a local array of the
+// caller, stays in registers (indexed at run time it would live in private memory, and
+// every access would pay a memory round trip).
+template <int NT, int NV>
+__device__ __forceinline__ void team_reduce(double *cv, int nmax_first,
+                                            double *red /*[32][NT/64]*/) {
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int v = 0; v < nv; ++v) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
         double x = cv[v];
         const bool mx = v < nmax_first;
         for (int off = 32; off >= 1; off >>= 1) {
@@ -97,7 +103,8 @@ __device__ void team_reduce(double *cv, int nv, int nmax_first, double *red /*[3
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int v = 0; v < nv; ++v) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
             const bool mx = v < nmax_first;
             double acc = red[v * (NT / 64)];
             for (int w = 1; w < NT / 64; ++w) {
@@ -326,7 +333,7 @@ __device__ __forceinline__ void team_infeas(int n, int m, const int32_t *arp, co
         team_sum<NT, 2>(sv, red);
         if (threadIdx.x == 0) col(j, sv[0], sv[1]);
     }
-    team_reduce<NT>(cv, 6, 3, red);
+    team_reduce<NT, 6>(cv, 3, red);
     if (threadIdx.x == 0) {
         out[INF_AVIOL] = cv[0];
         out[INF_QDX] = cv[1];
@@ -348,7 +355,10 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
                          const double *yrs, double *ra, double *rp, double *red,
                          const int32_t *lra, int nlra, const int32_t *lrp, int nlrp,
                          const double *dv, const double *dr) {
-    for (int v = 0; v < RA_NV; ++v) ra[v] = 0.0;
+    // accumulators in registers (local arrays with constant indices); the results go to
+    // ra and rp, which the out-of-line decision reads from memory, once at the end
+    double la[RA_NV], lp[RP_NV];
+    for (int v = 0; v < RA_NV; ++v) la[v] = 0.0;
     for (int i = threadIdx.x; i < m; i += NT) {
         if (arp[i + 1] - arp[i] > LONG_ROW) continue;
         double s0 = 0.0, s1 = 0.0;
@@ -358,7 +368,7 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
             s0 = s0 + a * x[cc];
             s1 = s1 + a * xbar[cc];
         }
-        kkt_row_contrib(i, s0, s1, b, rt, y, ybar, yrs, dr, ra);
+        kkt_row_contrib(i, s0, s1, b, rt, y, ybar, yrs, dr, la);
     }
     for (int q = 0; q < nlra; ++q) {
         const int i = lra[q];
@@ -370,10 +380,12 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
             sv[1] = sv[1] + a * xbar[cc];
         }
         team_sum<NT, 2>(sv, red);
-        if (threadIdx.x == 0) kkt_row_contrib(i, sv[0], sv[1], b, rt, y, ybar, yrs, dr, ra);
+        if (threadIdx.x == 0) kkt_row_contrib(i, sv[0], sv[1], b, rt, y, ybar, yrs, dr, la);
     }
-    team_reduce<NT>(ra, RA_NV, 4, red);
-    for (int v = 0; v < RP_NV; ++v) rp[v] = 0.0;
+    team_reduce<NT, RA_NV>(la, 4, red);
+    if (threadIdx.x == 0)
+        for (int v = 0; v < RA_NV; ++v) ra[v] = la[v];
+    for (int v = 0; v < RP_NV; ++v) lp[v] = 0.0;
     for (int j = threadIdx.x; j < n; j += NT) {
         if (prp[j + 1] - prp[j] > LONG_ROW) continue;
         double q[2] = {0.0, 0.0}, na[2] = {0.0, 0.0};
@@ -388,7 +400,7 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
                 na[1] = na[1] + a * ybar[cc - n];
             }
         }
-        kkt_col_contrib(j, q, na, c, l, u, x, xbar, xrs, dv, rp);
+        kkt_col_contrib(j, q, na, c, l, u, x, xbar, xrs, dv, lp);
     }
     for (int qq = 0; qq < nlrp; ++qq) {
         const int j = lrp[qq];
@@ -407,10 +419,12 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
         team_sum<NT, 4>(sv, red);
         if (threadIdx.x == 0) {
             double q[2] = {sv[0], sv[1]}, na[2] = {sv[2], sv[3]};
-            kkt_col_contrib(j, q, na, c, l, u, x, xbar, xrs, dv, rp);
+            kkt_col_contrib(j, q, na, c, l, u, x, xbar, xrs, dv, lp);
         }
     }
-    team_reduce<NT>(rp, RP_NV, 6, red);
+    team_reduce<NT, RP_NV>(lp, 6, red);
+    if (threadIdx.x == 0)
+        for (int v = 0; v < RP_NV; ++v) rp[v] = lp[v];
 }
 
 // The evaluation logic is called out of line: inlined, its exp/log/sqrt code would
@@ -858,7 +872,7 @@ __global__ __launch_bounds__(NT) void k_batch_norms(BatchDev a, int32_t maxit, d
                         acc[0] += sv[0] * sv[0];
                     }
                 }
-                team_reduce<NT>(acc, 1, 0, red);
+                team_reduce<NT, 1>(acc, 0, red);
                 if (t == 0) s_val[0] = acc[0];
                 __syncthreads();
                 lam = s_val[0];
@@ -886,7 +900,7 @@ __global__ __launch_bounds__(NT) void k_batch_norms(BatchDev a, int32_t maxit, d
                         acc[0] += sv[0] * sv[0];
                     }
                 }
-                team_reduce<NT>(acc, 1, 0, red);
+                team_reduce<NT, 1>(acc, 0, red);
                 if (t == 0) s_val[1] = sqrt(acc[0]);
                 __syncthreads();
                 const double nz = s_val[1];
@@ -929,7 +943,7 @@ __global__ __launch_bounds__(NT) void k_batch_norms(BatchDev a, int32_t maxit, d
                 acc[0] += v[j] * z[j];
                 acc[1] += z[j] * z[j];
             }
-            team_reduce<NT>(acc, 2, 0, red);
+            team_reduce<NT, 2>(acc, 0, red);
             if (t == 0) {
                 s_val[0] = acc[0];
                 s_val[1] = sqrt(acc[1]);
