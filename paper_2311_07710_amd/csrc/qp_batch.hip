@@ -355,8 +355,9 @@ __device__ void team_kkt(int n, int m, const int32_t *arp, const int32_t *acol, 
                          const double *yrs, double *ra, double *rp, double *red,
                          const int32_t *lra, int nlra, const int32_t *lrp, int nlrp,
                          const double *dv, const double *dr) {
-    // accumulators in registers (local arrays with constant indices); the results go to
-    // ra and rp, which the out-of-line decision reads from memory, once at the end
+    // accumulators in registers (local arrays with constant indices); each set goes to
+    // ra or rp, which the out-of-line decision reads from memory, right after its
+    // reduction (so that only one set is live at a time)
     double la[RA_NV], lp[RP_NV];
     for (int v = 0; v < RA_NV; ++v) la[v] = 0.0;
     for (int i = threadIdx.x; i < m; i += NT) {
